@@ -1,0 +1,204 @@
+/*
+ * qsim.h — C ABI of the MI355X (gfx950) full-state simulator.
+ *
+ * Operations follow Jones & Benjamin, "Distributed Simulation of Statevectors
+ * and Density Matrices" (arXiv:2311.01512); each declaration cites the section
+ * or equation that defines what it computes.  On one GPU the whole state is
+ * local, so every operation is the paper's local (non-exchanging) case.
+ *
+ * Conventions
+ *  - Qubit 0 is the least significant bit of an amplitude index
+ *    (Sec. "Notation").
+ *  - A statevector of N qubits holds 2^N complex amplitudes.  A density
+ *    matrix of N qubits is held as its Choi vector of 2^(2N) amplitudes,
+ *    entry k + l*2^N = rho[k][l] (Sec. "State representation").
+ *  - Amplitudes in device memory are interleaved (re, im) pairs of float
+ *    (QS_C64) or double (QS_C128).
+ *  - Host-side matrices are row-major interleaved (re, im) doubles.  For a
+ *    gate on targets t[0..n-1], bit q of a matrix row/column index belongs to
+ *    target t[q] (Sec. "Many-target gate").  Matrices need not be unitary, nor
+ *    Kraus maps trace preserving.
+ *  - Pauli codes: 0 = I, 1 = X, 2 = Y, 3 = Z.
+ *  - Every call returns a status (QS_OK = 0 or a negative QS_E_* code); on
+ *    failure nothing is modified and qs_last_error() describes the problem.
+ *    No exception crosses this boundary.
+ *  - Calls that update a state are asynchronous on the qureg's HIP stream.
+ *    Calls that return a scalar synchronise that stream before returning.
+ *  - Host arrays passed in are read during the call only; the caller keeps
+ *    ownership.  Calls on one qureg must not run concurrently from several
+ *    host threads.
+ */
+#ifndef QSIM_H
+#define QSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qs_qureg qs_qureg;
+typedef struct qs_circuit qs_circuit;
+
+enum { QS_C64 = 0, QS_C128 = 1 };
+
+enum {
+    QS_OK = 0,
+    QS_E_ARG = -1,     /* malformed argument (qubit out of range, duplicate, bad size) */
+    QS_E_PRECOND = -2, /* operation not valid for this qureg (e.g. density-only op on a statevector) */
+    QS_E_ALLOC = -3,   /* device or host allocation failed */
+    QS_E_HIP = -4,     /* a HIP runtime call failed */
+    QS_E_TYPE = -5     /* precision mismatch between quregs */
+};
+
+/* ---- quregs ------------------------------------------------------------ */
+
+/*
+ * Create a statevector (is_density = 0, 2^N amplitudes) or density matrix
+ * (is_density = 1, Choi vector of 2^(2N) amplitudes) of num_qubits qubits.
+ * device_ptr: NULL to let the library allocate (and later free) the
+ * amplitudes; otherwise a device buffer of at least 2^(N or 2N) amplitudes of
+ * the given precision that the caller owns and keeps alive until
+ * qs_destroy_qureg.  hip_stream: the hipStream_t all work on this qureg is
+ * ordered on (NULL = the null stream).  The state is not initialised.
+ * Sizes: 1 <= num_qubits, and the amplitude count must fit in device memory.
+ */
+int qs_create_qureg(int num_qubits, int is_density, int precision,
+                    void *device_ptr, void *hip_stream, qs_qureg **out);
+
+/* Free the qureg and, if the library allocated them, its amplitudes. */
+int qs_destroy_qureg(qs_qureg *q);
+
+/* Shape of a qureg; any output pointer may be NULL. */
+int qs_get_info(const qs_qureg *q, int *num_qubits, int *is_density,
+                int *precision, uint64_t *num_amps, void **device_ptr);
+
+/* Change the stream the qureg's work is ordered on (NULL = null stream). */
+int qs_set_stream(qs_qureg *q, void *hip_stream);
+
+/* Block until all work queued on the qureg's stream is done. */
+int qs_sync(qs_qureg *q);
+
+/* Thread-local description of the last failed call on this thread. */
+const char *qs_last_error(void);
+
+/* ---- initial states (Sec. "State representation") ------------------------ */
+
+/* |0..0>, or |0><0| for a density matrix. */
+int qs_init_zero_state(qs_qureg *q);
+
+/* |i>, or |i><i| (Choi entry i (2^N + 1)) for a density matrix; i < 2^N. */
+int qs_init_basis_state(qs_qureg *q, uint64_t index);
+
+/* |+..+>: every amplitude 2^(-N/2); for a density matrix every entry 2^-N. */
+int qs_init_plus_state(qs_qureg *q);
+
+/* rho = |psi><psi|: Choi entry j + k 2^N = psi_j conj(psi_k).  rho must be a
+ * density matrix and psi a statevector of the same size and precision. */
+int qs_init_pure_density(qs_qureg *rho, const qs_qureg *psi);
+
+/*
+ * Unnormalised pseudo-random state from a counter-based generator, defined
+ * entry by entry so that any entry can be regenerated independently:
+ * entry i = (u(2i) + i u(2i+1)) * 2^-ceil(L/2), L = number of index bits
+ * (N, or 2N for a density matrix), u(c) = 2 * (x >> 11) * 2^-53 - 1 with
+ * x = SplitMix64 output number c of a generator seeded with `seed`
+ * (Steele, Lea & Flood, OOPSLA 2014).  QS_C64 rounds the FP64 value to float.
+ */
+int qs_init_hashed_state(qs_qureg *q, uint64_t seed);
+
+/* Copy count amplitudes starting at index start between the device and a
+ * host array of 2*count doubles (re, im interleaved).  Synchronous. */
+int qs_set_amps(qs_qureg *q, uint64_t start, const double *re_im, uint64_t count);
+int qs_get_amps(const qs_qureg *q, uint64_t start, double *re_im, uint64_t count);
+
+/* ---- operators ------------------------------------------------------------ */
+
+/*
+ * Many-control many-target gate C_ctrls(M_targs) (Sec. "Many-control
+ * one-target gate", Eq. "serial_manyctrl_ctrl_cond"; Sec. "Many-target gate",
+ * Eq. "local_manyqb_amp_update"): every amplitude whose control bits are all 1
+ * is replaced by the matrix-weighted combination of the 2^n amplitudes that
+ * differ from it only on the targets; the others are untouched.  matrix is
+ * 2^n x 2^n (n = num_targs, 1 <= n <= 6), row-major (re, im) doubles.
+ * Controls and targets must be distinct qubits < N.  On a density matrix it
+ * applies rho -> U rho U^dagger (Eq. "unitary_on_vectorised_dens": U on the
+ * targets, conj(U) on the targets shifted by N, controls shifted alike).
+ */
+int qs_apply_multi_ctrl_multi_targ_unitary(qs_qureg *q, const int *ctrls, int num_ctrls,
+                                           const int *targs, int num_targs,
+                                           const double *matrix);
+
+/*
+ * Pauli gadget exp(i theta P), P = tensor of paulis[q] on targs[q]
+ * (Sec. "Pauli gadget"; Sec. "Phase gadget" when P has no X or Y).  Codes
+ * 0..3; identity entries are ignored.  On a density matrix the gadget is
+ * applied to the targets, then to the targets shifted by N with angle
+ * (-1)^(m+1) theta, m = number of Y (Alg. "distrib_dens_matr_specific_unitaries").
+ */
+int qs_apply_pauli_gadget(qs_qureg *q, const int *targs, const int *paulis,
+                          int num_targs, double theta);
+
+/*
+ * Superoperator S (4^n x 4^n, row-major (re, im) doubles) on targets t of a
+ * density matrix: the 2n-target gate S on the Choi vector with targets
+ * (t[0]..t[n-1], t[0]+N..t[n-1]+N) (Sec. "Kraus map", Alg.
+ * "distrib_dens_matr_kraus_map").  1 <= n <= 3.  Density matrices only.
+ */
+int qs_apply_superop(qs_qureg *q, const int *targs, int num_targs, const double *superop);
+
+/*
+ * Kraus map rho -> sum_m K_m rho K_m^dagger (Sec. "Kraus map"): builds
+ * S = sum_m conj(K_m) (x) K_m in FP64 on the host
+ * (Eq. "superop_from_kraus_map") and applies it as qs_apply_superop.
+ * kraus holds num_ops consecutive 2^n x 2^n row-major (re, im) matrices.
+ * 1 <= n <= 3, num_ops >= 1.  Density matrices only.
+ */
+int qs_apply_kraus_map(qs_qureg *q, const int *targs, int num_targs,
+                       const double *kraus, int num_ops);
+
+/* ---- calculations ---------------------------------------------------------- */
+
+/*
+ * Partial trace over targs (Sec. "Partial trace", Eq.
+ * "partial_trace_reduced_amp_def"): out[i] = sum_{v < 2^n} in[g(i, v)],
+ * g splicing the bits of v in at the traced qubits and again at those
+ * qubits + N.  The kept qubits keep their relative order.  in and out are
+ * density matrices of the same precision, out has N - n qubits, 1 <= n < N.
+ * Asynchronous on in's stream; out is ordered after it.
+ */
+int qs_calc_partial_trace(const qs_qureg *in, const int *targs, int num_targs, qs_qureg *out);
+
+/*
+ * Expectation of H = sum_t coeffs[t] (x)_q P(paulis[t*N + q]) (Sec. "Pauli
+ * string expectation value").  paulis: num_terms * N codes, term-major then
+ * qubit 0 first.  Density matrix: Tr(H rho) (Eq. "dens_expec_val_sum").
+ * Statevector: <psi|H|psi>.  Accumulated in FP64; *out_im is the imaginary
+ * part (zero up to rounding for Hermitian rho).  Either output may be NULL.
+ */
+int qs_calc_expec_pauli_sum(const qs_qureg *q, const int *paulis, const double *coeffs,
+                            int num_terms, double *out_re, double *out_im);
+
+/* Probability that measuring `qubit` gives `outcome` (0/1): the sum of |a_i|^2
+ * over i with that bit (Born rule), or of Re rho[k][k] for a density matrix.
+ * Not renormalised.  FP64 accumulation. */
+int qs_calc_prob_of_outcome(const qs_qureg *q, int qubit, int outcome, double *out);
+
+/* Statevector: sum |a_i|^2.  Density matrix: Re Tr(rho). */
+int qs_calc_total_prob(const qs_qureg *q, double *out);
+
+/* Density matrix: Tr(rho) as (re, im) (Sec. "Pauli string expectation value",
+ * trace of a Choi vector). */
+int qs_calc_trace(const qs_qureg *q, double *out_re, double *out_im);
+
+/* Density matrix: Tr(rho^2) = sum_{k,l} rho[k][l] rho[l][k] as (re, im). */
+int qs_calc_purity(const qs_qureg *q, double *out_re, double *out_im);
+
+/* Statevector: <a|b> = sum conj(a_i) b_i, FP64 accumulation. */
+int qs_calc_inner_product(const qs_qureg *a, const qs_qureg *b, double *out_re, double *out_im);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSIM_H */

@@ -1,0 +1,142 @@
+// Shared definitions of the gfx950 simulator library: amplitude types,
+// bit-index algebra, the qureg object and error reporting.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qsim.h"
+
+namespace qs {
+
+// ---- amplitudes --------------------------------------------------------------
+
+template <typename R> struct cplx_t;
+template <> struct cplx_t<float> { using type = float2; };
+template <> struct cplx_t<double> { using type = double2; };
+template <typename R> using C2 = typename cplx_t<R>::type;
+
+template <typename R> __device__ __forceinline__ C2<R> mk(R x, R y) { C2<R> c; c.x = x; c.y = y; return c; }
+
+// acc += m * v (complex)
+template <typename R>
+__device__ __forceinline__ void cmac(C2<R> &acc, const C2<R> m, const C2<R> v)
+{
+    acc.x = fma(m.x, v.x, acc.x);
+    acc.x = fma(-m.y, v.y, acc.x);
+    acc.y = fma(m.x, v.y, acc.y);
+    acc.y = fma(m.y, v.x, acc.y);
+}
+
+template <typename R>
+__device__ __forceinline__ C2<R> cmul(const C2<R> a, const C2<R> b)
+{
+    return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// ---- bit-index algebra (Alg. "bit_twiddles") ------------------------------------
+
+constexpr int kMaxInsert = 24;   // qubits spliced into a loop index by one launch
+
+// Splices zero bits into an index at ascending positions q_0 < q_1 < ...
+// (insertBits of the paper with b = 0), stored as the masks (1 << q_k) - 1.
+struct InsertPlan {
+    int n;
+    uint64_t low[kMaxInsert];
+};
+
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t g, const InsertPlan &p)
+{
+#pragma unroll 4
+    for (int k = 0; k < p.n; k++) {
+        const uint64_t lo = p.low[k];
+        g = (g & lo) | ((g & ~lo) << 1);
+    }
+    return g;
+}
+
+inline InsertPlan make_insert_plan(std::vector<int> qubits)
+{
+    InsertPlan p{};
+    std::vector<int> s = qubits;
+    for (size_t i = 1; i < s.size(); i++)       // insertion sort, tiny lists
+        for (size_t j = i; j > 0 && s[j - 1] > s[j]; j--) std::swap(s[j - 1], s[j]);
+    p.n = (int)s.size();
+    for (int k = 0; k < p.n; k++) p.low[k] = (1ULL << s[k]) - 1ULL;
+    return p;
+}
+
+// ---- qureg ---------------------------------------------------------------------
+
+}  // namespace qs
+
+struct qs_qureg {
+    int num_qubits;      // N
+    int is_density;
+    int precision;       // QS_C64 / QS_C128
+    int index_bits;      // N, or 2N for a density matrix
+    uint64_t num_amps;   // 2^index_bits
+    void *amps;          // device amplitudes
+    int owns_amps;
+    hipStream_t stream;
+    int device;
+    // scratch owned by the qureg
+    double *d_partials;  // per-block partial sums of reductions
+    double *d_result;    // final reduction results
+    double *h_result;    // pinned host copy of d_result
+    unsigned char *d_mat_ring;  // device copies of large gate matrices
+    unsigned char *h_mat_ring;  // pinned host staging of the same
+    size_t mat_ring_bytes;
+    size_t mat_ring_head;
+};
+
+namespace qs {
+
+constexpr int kReduceBlocks = 2048;       // partial sums per reduction pass
+constexpr int kResultSlots = 64;          // doubles in d_result / h_result
+constexpr size_t kMatRingBytes = 4u << 20;
+
+// ---- errors -------------------------------------------------------------------
+
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define QS_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::qs::fail(QS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define QS_LAUNCH_CHECK()                                                              \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess)                                                          \
+            return ::qs::fail(QS_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// Validates that qubits are distinct and inside [0, n).
+bool valid_qubits(const int *qs, int count, int n, std::string &why);
+
+// Launch geometry of grid-stride kernels: enough blocks to fill the chip
+// many times over, never more than the work needs.
+inline unsigned grid_for(uint64_t work, int block, uint64_t max_blocks = 256ull * 64)
+{
+    uint64_t b = (work + block - 1) / block;
+    if (b > max_blocks) b = max_blocks;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+// Stages `bytes` of host data into the qureg's device matrix ring and returns
+// the device address (ordered on the qureg's stream).
+int stage_matrix(qs_qureg *q, const void *host, size_t bytes, const void **dev);
+
+// Device reduction helpers, defined in reduce.hip.
+int finish_reduction(qs_qureg *q, int blocks, int width, double *out);
+
+}  // namespace qs

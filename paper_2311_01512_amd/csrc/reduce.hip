@@ -1,0 +1,597 @@
+// Read-only passes over a state: Born probabilities, norm, trace, purity,
+// Pauli-sum expectation values, inner products, and the partial trace.
+// All sums accumulate in FP64: per thread, then across the wavefront by
+// shuffles, across the block through LDS, and finally across blocks in a
+// fixed order, so a result does not depend on scheduling.
+#include "common.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <map>
+
+namespace qs {
+
+using cd = std::complex<double>;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sums (re, im) over the block; thread 0 receives the totals.
+__device__ __forceinline__ void block_sum2(double &re, double &im)
+{
+    __shared__ double s_re[16], s_im[16];
+    re = wave_sum(re);
+    im = wave_sum(im);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { s_re[wave] = re; s_im[wave] = im; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        double a = 0, b = 0;
+        for (int w = 0; w < nw; w++) { a += s_re[w]; b += s_im[w]; }
+        re = a;
+        im = b;
+    }
+}
+
+template <typename F>
+__global__ __launch_bounds__(256) void k_reduce(F f, uint64_t n, double *__restrict__ partials)
+{
+    double re = 0.0, im = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) f(i, re, im);
+    block_sum2(re, im);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = re;
+        partials[2 * blockIdx.x + 1] = im;
+    }
+}
+
+// Fixed-order sum of `blocks` (re, im) partials into result[2*slot..].
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int blocks,
+                                                   double *__restrict__ result, int slot)
+{
+    double re = 0.0, im = 0.0;
+    for (int b = threadIdx.x; b < blocks; b += blockDim.x) {
+        re += partials[2 * b];
+        im += partials[2 * b + 1];
+    }
+    block_sum2(re, im);
+    if (threadIdx.x == 0) {
+        result[2 * slot] = re;
+        result[2 * slot + 1] = im;
+    }
+}
+
+// ---- per-index contributions --------------------------------------------------------
+
+template <typename R> struct SumSq {
+    const C2<R> *a;
+    __device__ void operator()(uint64_t i, double &re, double &) const
+    {
+        const C2<R> x = a[i];
+        re += (double)x.x * x.x + (double)x.y * x.y;
+    }
+};
+
+// Born rule on a statevector: amplitudes whose bit q equals b.
+template <typename R> struct ProbSV {
+    const C2<R> *a;
+    uint64_t low;    // (1 << q) - 1
+    uint64_t bit;    // b << q
+    __device__ void operator()(uint64_t g, double &re, double &) const
+    {
+        const uint64_t i = (g & low) | ((g & ~low) << 1) | bit;
+        const C2<R> x = a[i];
+        re += (double)x.x * x.x + (double)x.y * x.y;
+    }
+};
+
+// Diagonal of a density matrix: rho[k][k] sits at Choi index k (2^N + 1);
+// optionally only k whose bit q equals b.
+template <typename R> struct DiagDM {
+    const C2<R> *a;
+    uint64_t stride; // 2^N + 1
+    uint64_t low, bit;
+    int conditioned;
+    __device__ void operator()(uint64_t g, double &re, double &im) const
+    {
+        const uint64_t k = conditioned ? ((g & low) | ((g & ~low) << 1) | bit) : g;
+        const C2<R> x = a[k * stride];
+        re += x.x;
+        im += x.y;
+    }
+};
+
+template <typename R> struct Inner {
+    const C2<R> *a, *b;
+    __device__ void operator()(uint64_t i, double &re, double &im) const
+    {
+        const C2<R> x = a[i], y = b[i];
+        re += (double)x.x * y.x + (double)x.y * y.y;
+        im += (double)x.x * y.y - (double)x.y * y.x;
+    }
+};
+
+constexpr int kTermsPerLaunch = 24;
+
+// Pauli terms sharing one flip mask: coefficient h_n eta_n (complex) and the
+// sign mask yz_n of each.
+struct TermGroup {
+    int count;
+    uint64_t yz[kTermsPerLaunch];
+    double cre[kTermsPerLaunch], cim[kTermsPerLaunch];
+};
+
+__device__ __forceinline__ void group_coeff(const TermGroup &t, uint64_t x, double &re, double &im)
+{
+    re = 0.0;
+    im = 0.0;
+    for (int n = 0; n < t.count; n++) {
+        const double s = (__popcll(x & t.yz[n]) & 1) ? -1.0 : 1.0;
+        re = fma(s, t.cre[n], re);
+        im = fma(s, t.cim[n], im);
+    }
+}
+
+// <psi| sum_n h_n P_n |psi> over the pairs (i, j = i ^ xy), using
+// (P psi)_i = beta_j a_j (Eq. "pauli_tensor_amp_update"), beta_x = eta (-1)^{popc(x & yz)}:
+// contribution conj(a_i) c(j) a_j + conj(a_j) c(i) a_i with c(x) = sum_n h_n beta^{(n)}_x.
+template <typename R> struct ExpecPairs {
+    const C2<R> *a;
+    uint64_t low, xy;
+    TermGroup t;
+    __device__ void operator()(uint64_t g, double &re, double &im) const
+    {
+        const uint64_t i = (g & low) | ((g & ~low) << 1);
+        const uint64_t j = i ^ xy;
+        const C2<R> ai = a[i], aj = a[j];
+        double ci_re, ci_im, cj_re, cj_im;
+        group_coeff(t, i, ci_re, ci_im);
+        group_coeff(t, j, cj_re, cj_im);
+        // conj(ai) * aj and conj(aj) * ai
+        const double p_re = (double)ai.x * aj.x + (double)ai.y * aj.y;
+        const double p_im = (double)ai.x * aj.y - (double)ai.y * aj.x;
+        re += cj_re * p_re - cj_im * p_im + ci_re * p_re + ci_im * p_im;
+        im += cj_re * p_im + cj_im * p_re - ci_re * p_im + ci_im * p_re;
+    }
+};
+
+// Diagonal terms (no X or Y): sum_i |a_i|^2 sum_n h_n (-1)^{popc(i & z_n)}.
+template <typename R> struct ExpecDiag {
+    const C2<R> *a;
+    TermGroup t;
+    __device__ void operator()(uint64_t i, double &re, double &im) const
+    {
+        const C2<R> x = a[i];
+        const double p = (double)x.x * x.x + (double)x.y * x.y;
+        double c_re, c_im;
+        group_coeff(t, i, c_re, c_im);
+        re += c_re * p;
+        im += c_im * p;
+    }
+};
+
+// Tr(H rho) (Eq. "dens_expec_val_sum"): the Pauli tensor element
+// P[l][k] is non-zero only for l = k ^ x, where it equals
+// i^{#Y} (-1)^{popc(k & yz)}; so each term gathers the 2^N entries
+// rho[k][k ^ x] = Choi[k + ((k ^ x) << N)] instead of visiting all 4^N.
+struct DMTerms {
+    int count;
+    uint64_t x[kTermsPerLaunch], yz[kTermsPerLaunch];
+    double cre[kTermsPerLaunch], cim[kTermsPerLaunch];   // h_n i^{#Y}
+};
+
+template <typename R> struct ExpecDM {
+    const C2<R> *a;
+    int N;
+    DMTerms t;
+    __device__ void operator()(uint64_t k, double &re, double &im) const
+    {
+        for (int n = 0; n < t.count; n++) {
+            const C2<R> b = a[k + ((k ^ t.x[n]) << N)];
+            const double s = (__popcll(k & t.yz[n]) & 1) ? -1.0 : 1.0;
+            const double c_re = s * t.cre[n], c_im = s * t.cim[n];
+            re += c_re * b.x - c_im * b.y;
+            im += c_re * b.y + c_im * b.x;
+        }
+    }
+};
+
+// ---- purity: Tr(rho^2) = sum_{k,l} rho[k][l] rho[l][k] ---------------------------------
+// Tiles of TS x TS entries: tile (kb, lb) with kb <= lb is read with k
+// fastest, its mirror with l fastest, the mirror goes through LDS so each
+// thread multiplies matching entries; off-diagonal tiles count twice.
+constexpr int kTile = 32;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_purity(const C2<R> *__restrict__ a, int N, int TS, uint64_t tiles_per_dim,
+                                                 uint64_t num_pairs, double *__restrict__ partials)
+{
+    __shared__ double2 mirror[kTile][kTile + 1];
+    const uint64_t d = 1ULL << N;
+    double re = 0.0, im = 0.0;
+    for (uint64_t p = blockIdx.x; p < num_pairs; p += gridDim.x) {
+        uint64_t lb = (uint64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+        while (lb * (lb + 1) / 2 > p) lb--;
+        while ((lb + 1) * (lb + 2) / 2 <= p) lb++;
+        const uint64_t kb = p - lb * (lb + 1) / 2;
+        const double w = (kb == lb) ? 1.0 : 2.0;
+        __syncthreads();
+        // mirror[kk][ll] = rho[l][k] = Choi[l + k d], loaded with ll fastest
+        for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
+            const int ll = e % TS, kk = e / TS;
+            const C2<R> v = a[(lb * TS + ll) + (kb * TS + kk) * d];
+            mirror[kk][ll] = make_double2(v.x, v.y);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
+            const int kk = e % TS, ll = e / TS;
+            const C2<R> v = a[(kb * TS + kk) + (lb * TS + ll) * d];
+            const double2 m = mirror[kk][ll];
+            re += w * ((double)v.x * m.x - (double)v.y * m.y);
+            im += w * ((double)v.x * m.y + (double)v.y * m.x);
+        }
+    }
+    (void)tiles_per_dim;
+    block_sum2(re, im);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = re;
+        partials[2 * blockIdx.x + 1] = im;
+    }
+}
+
+// ---- partial trace (Eq. "partial_trace_reduced_amp_def") -------------------------------
+struct SpreadBits {
+    int n;
+    uint64_t m[kMaxInsert];   // bit p of v -> (1 << t_p) | (1 << (t_p + N))
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_partial_trace(const C2<R> *__restrict__ in, C2<R> *__restrict__ out,
+                                                        uint64_t n_out, InsertPlan plan, SpreadBits sp)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t nv = 1ULL << sp.n;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_out; i += stride) {
+        const uint64_t g0 = insert_zeros(i, plan);
+        double re = 0.0, im = 0.0;
+        for (uint64_t v = 0; v < nv; v++) {
+            uint64_t g = g0;
+            for (int p = 0; p < sp.n; p++)
+                if ((v >> p) & 1) g |= sp.m[p];
+            const C2<R> x = in[g];
+            re += x.x;
+            im += x.y;
+        }
+        out[i] = mk<R>((R)re, (R)im);
+    }
+}
+
+// ---- host drivers ----------------------------------------------------------------------
+
+template <typename F>
+static int run_reduce(qs_qureg *q, const F &f, uint64_t n, int slot)
+{
+    const int blocks = (int)grid_for(n, 256, kReduceBlocks);
+    hipLaunchKernelGGL(k_reduce<F>, dim3(blocks), dim3(256), 0, q->stream, f, n, q->d_partials);
+    QS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, q->stream, (const double *)q->d_partials, blocks,
+                       q->d_result, slot);
+    QS_LAUNCH_CHECK();
+    return QS_OK;
+}
+
+// Copies result slots [0, nslots) back and waits.
+static int fetch(qs_qureg *q, int nslots)
+{
+    QS_HIP(hipMemcpyAsync(q->h_result, q->d_result, sizeof(double) * 2 * nslots, hipMemcpyDeviceToHost, q->stream));
+    QS_HIP(hipStreamSynchronize(q->stream));
+    return QS_OK;
+}
+
+int finish_reduction(qs_qureg *q, int blocks, int slot, double *out)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, q->stream, (const double *)q->d_partials, blocks,
+                       q->d_result, slot);
+    QS_LAUNCH_CHECK();
+    int rc = fetch(q, slot + 1);
+    if (rc != QS_OK) return rc;
+    out[0] = q->h_result[2 * slot];
+    out[1] = q->h_result[2 * slot + 1];
+    return QS_OK;
+}
+
+template <typename R>
+static int sum_sq(qs_qureg *q, double *out)
+{
+    int rc = run_reduce(q, SumSq<R>{(const C2<R> *)q->amps}, q->num_amps, 0);
+    if (rc == QS_OK) rc = fetch(q, 1);
+    if (rc == QS_OK) *out = q->h_result[0];
+    return rc;
+}
+
+template <typename R>
+static int diag_dm(qs_qureg *q, int qubit, int outcome, double *re, double *im)
+{
+    DiagDM<R> f{(const C2<R> *)q->amps, (1ULL << q->num_qubits) + 1ULL, 0, 0, 0};
+    uint64_t n = 1ULL << q->num_qubits;
+    if (qubit >= 0) {
+        f.low = (1ULL << qubit) - 1ULL;
+        f.bit = (uint64_t)outcome << qubit;
+        f.conditioned = 1;
+        n >>= 1;
+    }
+    int rc = run_reduce(q, f, n, 0);
+    if (rc == QS_OK) rc = fetch(q, 1);
+    if (rc != QS_OK) return rc;
+    *re = q->h_result[0];
+    if (im) *im = q->h_result[1];
+    return QS_OK;
+}
+
+template <typename R>
+static int prob_sv(qs_qureg *q, int qubit, int outcome, double *out)
+{
+    ProbSV<R> f{(const C2<R> *)q->amps, (1ULL << qubit) - 1ULL, (uint64_t)outcome << qubit};
+    int rc = run_reduce(q, f, q->num_amps >> 1, 0);
+    if (rc == QS_OK) rc = fetch(q, 1);
+    if (rc == QS_OK) *out = q->h_result[0];
+    return rc;
+}
+
+template <typename R>
+static int expec_sv(qs_qureg *q, const int *codes, const double *coeffs, int T, double *re, double *im)
+{
+    const int N = q->num_qubits;
+    // group the terms by their flip mask
+    std::map<uint64_t, std::vector<int>> groups;
+    std::vector<uint64_t> yzs(T);
+    std::vector<cd> cs(T);
+    const cd eta[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+    for (int t = 0; t < T; t++) {
+        uint64_t xy = 0, yz = 0;
+        int ny = 0;
+        for (int k = 0; k < N; k++) {
+            const int c = codes[(size_t)t * N + k];
+            if (c < 0 || c > 3) return fail(QS_E_ARG, "Pauli codes are 0..3");
+            if (c == 1 || c == 2) xy |= 1ULL << k;
+            if (c == 2 || c == 3) yz |= 1ULL << k;
+            if (c == 2) ny++;
+        }
+        groups[xy].push_back(t);
+        yzs[t] = yz;
+        cs[t] = coeffs[t] * eta[ny & 3];
+    }
+    double acc_re = 0.0, acc_im = 0.0;
+    int slot = 0;
+    auto flush = [&]() -> int {
+        if (slot == 0) return QS_OK;
+        int rc = fetch(q, slot);
+        if (rc != QS_OK) return rc;
+        for (int s = 0; s < slot; s++) {
+            acc_re += q->h_result[2 * s];
+            acc_im += q->h_result[2 * s + 1];
+        }
+        slot = 0;
+        return QS_OK;
+    };
+    for (auto &kv : groups) {
+        const uint64_t xy = kv.first;
+        const std::vector<int> &ts = kv.second;
+        for (size_t b = 0; b < ts.size(); b += kTermsPerLaunch) {
+            TermGroup g{};
+            g.count = (int)std::min<size_t>(kTermsPerLaunch, ts.size() - b);
+            for (int n = 0; n < g.count; n++) {
+                g.yz[n] = yzs[ts[b + n]];
+                g.cre[n] = cs[ts[b + n]].real();
+                g.cim[n] = cs[ts[b + n]].imag();
+            }
+            int rc;
+            if (xy == 0) {
+                rc = run_reduce(q, ExpecDiag<R>{(const C2<R> *)q->amps, g}, q->num_amps, slot);
+            } else {
+                int lb = 0;
+                while (!((xy >> lb) & 1ULL)) lb++;
+                rc = run_reduce(q, ExpecPairs<R>{(const C2<R> *)q->amps, (1ULL << lb) - 1ULL, xy, g},
+                                q->num_amps >> 1, slot);
+            }
+            if (rc != QS_OK) return rc;
+            if (++slot == kResultSlots / 2) {
+                rc = flush();
+                if (rc != QS_OK) return rc;
+            }
+        }
+    }
+    int rc = flush();
+    if (rc != QS_OK) return rc;
+    *re = acc_re;
+    *im = acc_im;
+    return QS_OK;
+}
+
+template <typename R>
+static int expec_dm(qs_qureg *q, const int *codes, const double *coeffs, int T, double *re, double *im)
+{
+    const int N = q->num_qubits;
+    const cd eta[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+    double acc_re = 0.0, acc_im = 0.0;
+    for (int b = 0; b < T; b += kTermsPerLaunch) {
+        DMTerms g{};
+        g.count = std::min(kTermsPerLaunch, T - b);
+        for (int n = 0; n < g.count; n++) {
+            uint64_t x = 0, yz = 0;
+            int ny = 0;
+            for (int k = 0; k < N; k++) {
+                const int c = codes[(size_t)(b + n) * N + k];
+                if (c < 0 || c > 3) return fail(QS_E_ARG, "Pauli codes are 0..3");
+                if (c == 1 || c == 2) x |= 1ULL << k;
+                if (c == 2 || c == 3) yz |= 1ULL << k;
+                if (c == 2) ny++;
+            }
+            const cd c = coeffs[b + n] * eta[ny & 3];
+            g.x[n] = x;
+            g.yz[n] = yz;
+            g.cre[n] = c.real();
+            g.cim[n] = c.imag();
+        }
+        int rc = run_reduce(q, ExpecDM<R>{(const C2<R> *)q->amps, N, g}, 1ULL << N, 0);
+        if (rc == QS_OK) rc = fetch(q, 1);
+        if (rc != QS_OK) return rc;
+        acc_re += q->h_result[0];
+        acc_im += q->h_result[1];
+    }
+    *re = acc_re;
+    *im = acc_im;
+    return QS_OK;
+}
+
+template <typename R>
+static int purity(qs_qureg *q, double *re, double *im)
+{
+    const int N = q->num_qubits;
+    const uint64_t d = 1ULL << N;
+    const int TS = (int)std::min<uint64_t>(d, kTile);
+    const uint64_t T = d / TS;
+    const uint64_t pairs = T * (T + 1) / 2;
+    const int blocks = (int)std::min<uint64_t>(pairs, kReduceBlocks);
+    hipLaunchKernelGGL(k_purity<R>, dim3(blocks), dim3(256), 0, q->stream, (const C2<R> *)q->amps, N, TS, T, pairs,
+                       q->d_partials);
+    QS_LAUNCH_CHECK();
+    double out[2];
+    int rc = finish_reduction(q, blocks, 0, out);
+    if (rc != QS_OK) return rc;
+    *re = out[0];
+    if (im) *im = out[1];
+    return QS_OK;
+}
+
+template <typename R>
+static int partial_trace(const qs_qureg *in, const std::vector<int> &t, qs_qureg *out)
+{
+    const int N = in->num_qubits, n = (int)t.size();
+    std::vector<int> both(t);
+    for (int x : t) both.push_back(x + N);
+    InsertPlan plan = make_insert_plan(both);
+    SpreadBits sp{};
+    sp.n = n;
+    for (int p = 0; p < n; p++) sp.m[p] = (1ULL << t[p]) | (1ULL << (t[p] + N));
+    const uint64_t n_out = out->num_amps;
+    hipLaunchKernelGGL(k_partial_trace<R>, dim3(grid_for(n_out, 256)), dim3(256), 0, in->stream,
+                       (const C2<R> *)in->amps, (C2<R> *)out->amps, n_out, plan, sp);
+    QS_LAUNCH_CHECK();
+    return QS_OK;
+}
+
+}  // namespace qs
+
+using namespace qs;
+
+extern "C" {
+
+int qs_calc_total_prob(const qs_qureg *cq, double *out)
+{
+    qs_qureg *q = const_cast<qs_qureg *>(cq);
+    if (!q || !out) return fail(QS_E_ARG, "null argument");
+    if (q->is_density)
+        return q->precision == QS_C64 ? diag_dm<float>(q, -1, 0, out, nullptr) : diag_dm<double>(q, -1, 0, out, nullptr);
+    return q->precision == QS_C64 ? sum_sq<float>(q, out) : sum_sq<double>(q, out);
+}
+
+int qs_calc_prob_of_outcome(const qs_qureg *cq, int qubit, int outcome, double *out)
+{
+    qs_qureg *q = const_cast<qs_qureg *>(cq);
+    if (!q || !out) return fail(QS_E_ARG, "null argument");
+    if (qubit < 0 || qubit >= q->num_qubits) return fail(QS_E_ARG, "qubit out of range");
+    if (outcome != 0 && outcome != 1) return fail(QS_E_ARG, "outcome must be 0 or 1");
+    if (q->is_density)
+        return q->precision == QS_C64 ? diag_dm<float>(q, qubit, outcome, out, nullptr)
+                                      : diag_dm<double>(q, qubit, outcome, out, nullptr);
+    return q->precision == QS_C64 ? prob_sv<float>(q, qubit, outcome, out) : prob_sv<double>(q, qubit, outcome, out);
+}
+
+int qs_calc_trace(const qs_qureg *cq, double *out_re, double *out_im)
+{
+    qs_qureg *q = const_cast<qs_qureg *>(cq);
+    if (!q || !out_re) return fail(QS_E_ARG, "null argument");
+    if (!q->is_density) return fail(QS_E_PRECOND, "trace is defined here for density matrices");
+    return q->precision == QS_C64 ? diag_dm<float>(q, -1, 0, out_re, out_im) : diag_dm<double>(q, -1, 0, out_re, out_im);
+}
+
+int qs_calc_purity(const qs_qureg *cq, double *out_re, double *out_im)
+{
+    qs_qureg *q = const_cast<qs_qureg *>(cq);
+    if (!q || !out_re) return fail(QS_E_ARG, "null argument");
+    if (!q->is_density) return fail(QS_E_PRECOND, "purity is computed for density matrices");
+    return q->precision == QS_C64 ? purity<float>(q, out_re, out_im) : purity<double>(q, out_re, out_im);
+}
+
+int qs_calc_expec_pauli_sum(const qs_qureg *cq, const int *paulis, const double *coeffs, int num_terms,
+                            double *out_re, double *out_im)
+{
+    qs_qureg *q = const_cast<qs_qureg *>(cq);
+    if (!q) return fail(QS_E_ARG, "null qureg");
+    if (num_terms < 0 || (num_terms > 0 && (!paulis || !coeffs))) return fail(QS_E_ARG, "bad Pauli sum");
+    double re = 0.0, im = 0.0;
+    int rc = QS_OK;
+    if (num_terms > 0) {
+        if (q->is_density)
+            rc = q->precision == QS_C64 ? expec_dm<float>(q, paulis, coeffs, num_terms, &re, &im)
+                                        : expec_dm<double>(q, paulis, coeffs, num_terms, &re, &im);
+        else
+            rc = q->precision == QS_C64 ? expec_sv<float>(q, paulis, coeffs, num_terms, &re, &im)
+                                        : expec_sv<double>(q, paulis, coeffs, num_terms, &re, &im);
+    }
+    if (rc != QS_OK) return rc;
+    if (out_re) *out_re = re;
+    if (out_im) *out_im = im;
+    return QS_OK;
+}
+
+int qs_calc_inner_product(const qs_qureg *ca, const qs_qureg *cb, double *out_re, double *out_im)
+{
+    qs_qureg *a = const_cast<qs_qureg *>(ca);
+    qs_qureg *b = const_cast<qs_qureg *>(cb);
+    if (!a || !b) return fail(QS_E_ARG, "null qureg");
+    if (a->is_density || b->is_density) return fail(QS_E_PRECOND, "inner products of statevectors only");
+    if (a->num_qubits != b->num_qubits) return fail(QS_E_ARG, "qubit counts differ");
+    if (a->precision != b->precision) return fail(QS_E_TYPE, "precisions differ");
+    if (a->stream != b->stream) QS_HIP(hipStreamSynchronize(b->stream));
+    int rc = a->precision == QS_C64
+                 ? run_reduce(a, Inner<float>{(const float2 *)a->amps, (const float2 *)b->amps}, a->num_amps, 0)
+                 : run_reduce(a, Inner<double>{(const double2 *)a->amps, (const double2 *)b->amps}, a->num_amps, 0);
+    if (rc == QS_OK) rc = fetch(a, 1);
+    if (rc != QS_OK) return rc;
+    if (out_re) *out_re = a->h_result[0];
+    if (out_im) *out_im = a->h_result[1];
+    return QS_OK;
+}
+
+int qs_calc_partial_trace(const qs_qureg *in, const int *targs, int num_targs, qs_qureg *out)
+{
+    if (!in || !out) return fail(QS_E_ARG, "null qureg");
+    if (!in->is_density || !out->is_density) return fail(QS_E_PRECOND, "partial trace needs density matrices");
+    if (in->precision != out->precision) return fail(QS_E_TYPE, "precisions differ");
+    if (num_targs < 1 || num_targs >= in->num_qubits || !targs)
+        return fail(QS_E_ARG, "trace out between 1 and N-1 qubits");
+    if (out->num_qubits != in->num_qubits - num_targs)
+        return fail(QS_E_ARG, "output must have N - n qubits");
+    if (in->amps == out->amps) return fail(QS_E_ARG, "input and output must not alias");
+    std::string why;
+    if (!valid_qubits(targs, num_targs, in->num_qubits, why)) return fail(QS_E_ARG, why);
+    // out's pending work must finish before in's stream overwrites it, and
+    // out's later work must follow the trace
+    if (out->stream != in->stream) QS_HIP(hipStreamSynchronize(out->stream));
+    std::vector<int> t(targs, targs + num_targs);
+    int rc = in->precision == QS_C64 ? partial_trace<float>(in, t, out) : partial_trace<double>(in, t, out);
+    if (rc != QS_OK) return rc;
+    if (out->stream != in->stream) QS_HIP(hipStreamSynchronize(in->stream));
+    return QS_OK;
+}
+
+}  // extern "C"

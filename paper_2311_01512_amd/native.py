@@ -1,0 +1,229 @@
+"""ctypes binding of libqsim.so: the C entry points under the same names,
+argument marshalling only.  Importing this module raises if the HIP library
+has not been built; there is no fallback implementation.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqsim.so")
+HEADER = os.path.join(HERE, "..", "include", "qsim.h")
+
+QS_C64, QS_C128 = 0, 1
+QS_OK, QS_E_ARG, QS_E_PRECOND, QS_E_ALLOC, QS_E_HIP, QS_E_TYPE = 0, -1, -2, -3, -4, -5
+
+_ERRS = {QS_E_ARG: ValueError, QS_E_PRECOND: ValueError, QS_E_ALLOC: MemoryError, QS_E_TYPE: TypeError}
+
+
+class QsError(RuntimeError):
+    pass
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2311_01512_amd/build.py "
+                          "(or __graft_entry__.build()); there is no fallback path")
+    return C.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+_P, _I, _D, _U64 = C.c_void_p, C.c_int, C.c_double, C.c_uint64
+_PP = C.POINTER(C.c_void_p)
+_PD = C.POINTER(C.c_double)
+
+_SIGS = {
+    "qs_create_qureg": [_I, _I, _I, _P, _P, _PP],
+    "qs_destroy_qureg": [_P],
+    "qs_get_info": [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_uint64), _PP],
+    "qs_set_stream": [_P, _P],
+    "qs_sync": [_P],
+    "qs_init_zero_state": [_P],
+    "qs_init_basis_state": [_P, _U64],
+    "qs_init_plus_state": [_P],
+    "qs_init_pure_density": [_P, _P],
+    "qs_init_hashed_state": [_P, _U64],
+    "qs_set_amps": [_P, _U64, _P, _U64],
+    "qs_get_amps": [_P, _U64, _P, _U64],
+    "qs_apply_multi_ctrl_multi_targ_unitary": [_P, _P, _I, _P, _I, _P],
+    "qs_apply_pauli_gadget": [_P, _P, _P, _I, _D],
+    "qs_apply_superop": [_P, _P, _I, _P],
+    "qs_apply_kraus_map": [_P, _P, _I, _P, _I],
+    "qs_calc_partial_trace": [_P, _P, _I, _P],
+    "qs_calc_expec_pauli_sum": [_P, _P, _P, _I, _PD, _PD],
+    "qs_calc_prob_of_outcome": [_P, _I, _I, _PD],
+    "qs_calc_total_prob": [_P, _PD],
+    "qs_calc_trace": [_P, _PD, _PD],
+    "qs_calc_purity": [_P, _PD, _PD],
+    "qs_calc_inner_product": [_P, _P, _PD, _PD],
+}
+
+for _name, _args in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+lib.qs_last_error.argtypes = []
+lib.qs_last_error.restype = C.c_char_p
+
+
+def check(rc, what=""):
+    if rc != QS_OK:
+        msg = lib.qs_last_error().decode(errors="replace")
+        raise _ERRS.get(rc, QsError)(f"{what}: {msg} (status {rc})")
+    return rc
+
+
+def ints(xs):
+    return np.ascontiguousarray(np.asarray(list(xs), dtype=np.int32))
+
+
+def ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def cmatrix(m):
+    """Complex matrix -> contiguous interleaved (re, im) float64 array."""
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+    return m.view(np.float64)
+
+
+# ---- thin wrappers with the C names ----------------------------------------
+
+def qs_create_qureg(num_qubits, is_density, precision, device_ptr=None, hip_stream=None):
+    out = C.c_void_p()
+    check(lib.qs_create_qureg(num_qubits, int(bool(is_density)), precision, device_ptr, hip_stream,
+                              C.byref(out)), "qs_create_qureg")
+    return out
+
+
+def qs_destroy_qureg(q):
+    check(lib.qs_destroy_qureg(q), "qs_destroy_qureg")
+
+
+def qs_set_stream(q, hip_stream):
+    check(lib.qs_set_stream(q, hip_stream), "qs_set_stream")
+
+
+def qs_sync(q):
+    check(lib.qs_sync(q), "qs_sync")
+
+
+def qs_init_zero_state(q):
+    check(lib.qs_init_zero_state(q), "qs_init_zero_state")
+
+
+def qs_init_basis_state(q, index):
+    check(lib.qs_init_basis_state(q, index), "qs_init_basis_state")
+
+
+def qs_init_plus_state(q):
+    check(lib.qs_init_plus_state(q), "qs_init_plus_state")
+
+
+def qs_init_pure_density(rho, psi):
+    check(lib.qs_init_pure_density(rho, psi), "qs_init_pure_density")
+
+
+def qs_init_hashed_state(q, seed):
+    check(lib.qs_init_hashed_state(q, seed), "qs_init_hashed_state")
+
+
+def qs_set_amps(q, start, amps):
+    a = np.ascontiguousarray(np.asarray(amps, dtype=np.complex128))
+    check(lib.qs_set_amps(q, start, ptr(a), a.size), "qs_set_amps")
+
+
+def qs_get_amps(q, start, count):
+    a = np.empty(count, dtype=np.complex128)
+    check(lib.qs_get_amps(q, start, ptr(a), count), "qs_get_amps")
+    return a
+
+
+def _square(m, dim, what):
+    if np.shape(m) != (dim, dim):
+        raise ValueError(f"{what} must be {dim} x {dim}, got shape {np.shape(m)}")
+
+
+def qs_apply_multi_ctrl_multi_targ_unitary(q, ctrls, targs, matrix):
+    c, t = ints(ctrls), ints(targs)
+    _square(matrix, 1 << t.size, "matrix")
+    m = cmatrix(matrix)
+    check(lib.qs_apply_multi_ctrl_multi_targ_unitary(q, ptr(c), c.size, ptr(t), t.size, ptr(m)),
+          "qs_apply_multi_ctrl_multi_targ_unitary")
+
+
+def qs_apply_pauli_gadget(q, targs, paulis, theta):
+    t, p = ints(targs), ints(paulis)
+    if t.size != p.size:
+        raise ValueError("targs and paulis differ in length")
+    check(lib.qs_apply_pauli_gadget(q, ptr(t), ptr(p), t.size, float(theta)), "qs_apply_pauli_gadget")
+
+
+def qs_apply_superop(q, targs, superop):
+    t = ints(targs)
+    _square(superop, 1 << (2 * t.size), "superoperator")
+    s = cmatrix(superop)
+    check(lib.qs_apply_superop(q, ptr(t), t.size, ptr(s)), "qs_apply_superop")
+
+
+def qs_apply_kraus_map(q, targs, kraus):
+    t = ints(targs)
+    k = np.ascontiguousarray(np.asarray(kraus, dtype=np.complex128))
+    if k.ndim != 3 or k.shape[1:] != (1 << t.size, 1 << t.size):
+        raise ValueError(f"Kraus operators must have shape (M, {1 << t.size}, {1 << t.size})")
+    check(lib.qs_apply_kraus_map(q, ptr(t), t.size, ptr(k.view(np.float64)), k.shape[0]), "qs_apply_kraus_map")
+
+
+def qs_calc_partial_trace(q_in, targs, q_out):
+    t = ints(targs)
+    check(lib.qs_calc_partial_trace(q_in, ptr(t), t.size, q_out), "qs_calc_partial_trace")
+
+
+def qs_get_info(q):
+    n, d, p, na, ptr_ = C.c_int(), C.c_int(), C.c_int(), C.c_uint64(), C.c_void_p()
+    check(lib.qs_get_info(q, C.byref(n), C.byref(d), C.byref(p), C.byref(na), C.byref(ptr_)), "qs_get_info")
+    return {"num_qubits": n.value, "is_density": d.value, "precision": p.value, "num_amps": na.value,
+            "device_ptr": ptr_.value}
+
+
+def qs_calc_expec_pauli_sum(q, paulis, coeffs):
+    p = np.ascontiguousarray(np.asarray(paulis, dtype=np.int32))
+    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+    if p.size != c.size * qs_get_info(q)["num_qubits"]:
+        raise ValueError("need num_terms * num_qubits Pauli codes")
+    re, im = C.c_double(), C.c_double()
+    check(lib.qs_calc_expec_pauli_sum(q, ptr(p), ptr(c), c.size, C.byref(re), C.byref(im)),
+          "qs_calc_expec_pauli_sum")
+    return complex(re.value, im.value)
+
+
+def qs_calc_prob_of_outcome(q, qubit, outcome):
+    out = C.c_double()
+    check(lib.qs_calc_prob_of_outcome(q, qubit, outcome, C.byref(out)), "qs_calc_prob_of_outcome")
+    return out.value
+
+
+def qs_calc_total_prob(q):
+    out = C.c_double()
+    check(lib.qs_calc_total_prob(q, C.byref(out)), "qs_calc_total_prob")
+    return out.value
+
+
+def qs_calc_trace(q):
+    re, im = C.c_double(), C.c_double()
+    check(lib.qs_calc_trace(q, C.byref(re), C.byref(im)), "qs_calc_trace")
+    return complex(re.value, im.value)
+
+
+def qs_calc_purity(q):
+    re, im = C.c_double(), C.c_double()
+    check(lib.qs_calc_purity(q, C.byref(re), C.byref(im)), "qs_calc_purity")
+    return complex(re.value, im.value)
+
+
+def qs_calc_inner_product(a, b):
+    re, im = C.c_double(), C.c_double()
+    check(lib.qs_calc_inner_product(a, b, C.byref(re), C.byref(im)), "qs_calc_inner_product")
+    return complex(re.value, im.value)
