@@ -22,6 +22,11 @@ class QsError(RuntimeError):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime.  Loading torch first makes
+    # libqsim.so bind to that same runtime (same soname), so device pointers
+    # and streams from torch are valid here; otherwise two runtimes would
+    # coexist in the process.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2311_01512_amd/build.py "
                           "(or __graft_entry__.build()); there is no fallback path")
