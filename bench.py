@@ -33,7 +33,27 @@ def parse():
     ap.add_argument("--gates", type=int, default=500)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="short run for hardware-counter collection: one torch copy of 2 GiB "
+                         "(the calibration kernel of known traffic), then one pass of the circuit")
     return ap.parse_args()
+
+
+def pmc_probe(args):
+    import torch
+    import synth
+    import paper_2311_01512_amd as qs
+    n = args.qubits
+    src = torch.zeros(1 << 28, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)                      # reads 2 GiB, writes 2 GiB
+    torch.cuda.synchronize()
+    del src, dst
+    ops = synth.config2_circuit(num_qubits=n, num_gates=args.gates)
+    q = qs.Qureg(n, precision="c128").init_hashed(11)
+    q.run_ops(ops)
+    q.sync()
+    print(json.dumps({"pmc_probe": "done", "gates": len(ops), "num_qubits": n}), flush=True)
 
 
 def op_kind(op):
@@ -99,6 +119,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.pmc_probe:
+        pmc_probe(args)
+        return
     import torch
     import synth
     import paper_2311_01512_amd as qs

@@ -96,7 +96,7 @@ struct qs_qureg {
 
 namespace qs {
 
-constexpr int kReduceBlocks = 2048;       // partial sums per reduction pass
+constexpr int kReduceBlocks = 16384;      // partial sums per reduction pass
 constexpr int kResultSlots = 64;          // doubles in d_result / h_result
 constexpr size_t kMatRingBytes = 4u << 20;
 
@@ -122,9 +122,11 @@ int fail(int code, const std::string &msg);
 // Validates that qubits are distinct and inside [0, n).
 bool valid_qubits(const int *qs, int count, int n, std::string &why);
 
-// Launch geometry of grid-stride kernels: enough blocks to fill the chip
-// many times over, never more than the work needs.
-inline unsigned grid_for(uint64_t work, int block, uint64_t max_blocks = 256ull * 64)
+// Launch geometry of the streaming kernels: one unit of work per thread (a
+// grid of ceil(work / block) blocks), which measured faster on gfx950 than
+// fewer blocks striding over the array; the kernels keep a grid-stride loop
+// only for work beyond max_blocks * block.
+inline unsigned grid_for(uint64_t work, int block, uint64_t max_blocks = 1ull << 30)
 {
     uint64_t b = (work + block - 1) / block;
     if (b > max_blocks) b = max_blocks;

@@ -86,6 +86,10 @@ __global__ __launch_bounds__(256) void k_gate(C2<R> *__restrict__ a, uint64_t nu
 
 // Pauli gadget exp(i theta P) (Sec. "Pauli gadget"): for the pair
 // (i, j = i ^ xy) enumerated once, with c = i sin(theta) eta,
+// Pairs are enumerated by splicing a zero at the HIGHEST flipped bit, so
+// consecutive lanes touch consecutive amplitudes on both sides of the pair
+// and every cache line is consumed by one wavefront (splicing at the lowest
+// flipped bit would leave half of each line to a distant thread).
 //   a_i <- cos(theta) a_i + c (-1)^{popc(j & yz)} a_j
 //   a_j <- cos(theta) a_j + c (-1)^{popc(i & yz)} a_i.
 template <typename R>
@@ -236,9 +240,8 @@ int apply_raw_gadget(qs_qureg *q, const std::vector<int> &targs, const std::vect
         // c = i sin(theta) eta, eta = i^{#Y}
         const cd eta[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
         const cd c = cd(0, sn) * eta[ny & 3];
-        int lb = 0;
-        while (!((xy >> lb) & 1ULL)) lb++;
-        const uint64_t low = (1ULL << lb) - 1ULL;
+        const int hb = 63 - __builtin_clzll(xy);
+        const uint64_t low = (1ULL << hb) - 1ULL;
         const uint64_t np = q->num_amps >> 1;
         if (q->precision == QS_C64)
             hipLaunchKernelGGL(k_gadget_pairs<float>, dim3(grid_for(np, block)), dim3(block), 0, q->stream,

@@ -396,9 +396,8 @@ static int expec_sv(qs_qureg *q, const int *codes, const double *coeffs, int T, 
             if (xy == 0) {
                 rc = run_reduce(q, ExpecDiag<R>{(const C2<R> *)q->amps, g}, q->num_amps, slot);
             } else {
-                int lb = 0;
-                while (!((xy >> lb) & 1ULL)) lb++;
-                rc = run_reduce(q, ExpecPairs<R>{(const C2<R> *)q->amps, (1ULL << lb) - 1ULL, xy, g},
+                const int hb = 63 - __builtin_clzll(xy);   // see k_gadget_pairs
+                rc = run_reduce(q, ExpecPairs<R>{(const C2<R> *)q->amps, (1ULL << hb) - 1ULL, xy, g},
                                 q->num_amps >> 1, slot);
             }
             if (rc != QS_OK) return rc;
