@@ -56,10 +56,28 @@ def pmc_probe(args):
     print(json.dumps({"pmc_probe": "done", "gates": len(ops), "num_qubits": n}), flush=True)
 
 
-def op_kind(op):
+def op_kind(op, real):
+    """Name of the kernel that carries an op on the per-gate path."""
     if op["op"] == "gadget":
-        return "gadget"
-    return f"gate{len(op['targs'])}"
+        xy = any(p in (1, 2) for p in op["paulis"])
+        return f"k_gadget_pairs<{real}>" if xy else f"k_gadget_diag<{real}>"
+    return f"k_gate<{real}, {len(op['targs'])}>"
+
+
+def measured_traffic(kernel, n):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when none exists or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(f"{kernel}@{n}q")
+    if not rec:
+        return None
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:len(rec["sha256_prefix"])] != rec["sha256_prefix"]:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def op_updates(op, n):
@@ -88,7 +106,7 @@ def time_path(q, ops, steps, warmup, torch):
         torch.cuda.synchronize()
         total += time.perf_counter() - t0
         for op, (a, b) in zip(ops, ev):
-            k = op_kind(op)
+            k = op_kind(op, "double" if q.precision == "c128" else "float")
             c = per_kind.setdefault(k, [0, 0.0, 0])
             c[0] += 1
             c[1] += a.elapsed_time(b)
@@ -170,7 +188,7 @@ def main():
                                "(Haar 1q, 2-target Haar with 0-3 controls, Pauli gadgets weight 1-N)",
                    "num_qubits": n, "gates": len(ops), "path": "plain per-gate complex128"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(k_name, n),
                      "kernel": k_name, "avg_launch_ms": avg_ms, "bytes_per_launch": bytes_per_launch},
         "plain_c128": {"value": logical / t128, "ms_per_step": t128 * 1e3,
                        "per_kind": {k: {"launches": v[0], "avg_ms": v[1] / v[0],
