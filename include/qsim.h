@@ -197,6 +197,42 @@ int qs_calc_purity(const qs_qureg *q, double *out_re, double *out_im);
 /* Statevector: <a|b> = sum conj(a_i) b_i, FP64 accumulation. */
 int qs_calc_inner_product(const qs_qureg *a, const qs_qureg *b, double *out_re, double *out_im);
 
+/* ---- circuits: recorded op lists, optionally fused into dense blocks ------- */
+
+/*
+ * A circuit records statevector operators for later application.  Compiling
+ * it with fuse_k >= 2 merges operators into dense blocks of at most fuse_k
+ * qubits (2 <= fuse_k <= 6): an operator joins the current block when the
+ * block's qubit set stays within fuse_k qubits and the operator commutes
+ * with every operator it is moved across (disjoint qubits).  A block's matrix
+ * is the FP64 product of its members, each written densely on the block's
+ * qubits (controls expanded, a gadget as cos(theta) 1 + i sin(theta) P, Sec.
+ * "Pauli gadget").  Operators on more than fuse_k qubits stay single passes.
+ * fuse_k = 0 keeps one pass per operator (the plain per-gate method).
+ * Blocks of 4-6 qubits on complex64 run as FP32 MFMA GEMMs.
+ * The circuit owns device copies of its matrices for one precision; it must
+ * outlive the work queued by qs_apply_circuit.
+ */
+int qs_circuit_create(int num_qubits, qs_circuit **out);
+int qs_circuit_destroy(qs_circuit *c);
+/* Same arguments and meaning as qs_apply_multi_ctrl_multi_targ_unitary. */
+int qs_circuit_add_unitary(qs_circuit *c, const int *ctrls, int num_ctrls, const int *targs, int num_targs,
+                           const double *matrix);
+/* Same arguments and meaning as qs_apply_pauli_gadget. */
+int qs_circuit_add_pauli_gadget(qs_circuit *c, const int *targs, const int *paulis, int num_targs, double theta);
+/* Builds the pass list (see above); precision selects the device matrix layout. */
+int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision);
+/* Pass statistics of the compiled circuit; any pointer may be NULL.
+ * logical_updates: amplitude updates under the plain per-gate accounting
+ * (2^(N-s) per s-controlled gate, 2^N per gadget) of the recorded ops;
+ * blocks_by_width: array of 7 counters, passes by number of qubits (index
+ * 0 counts single gadget passes). */
+int qs_circuit_stats(const qs_circuit *c, int *num_ops, int *num_passes, uint64_t *logical_updates,
+                     int *blocks_by_width);
+/* Applies the compiled circuit to a statevector of the circuit's size and
+ * compiled precision, in order, on the qureg's stream. */
+int qs_apply_circuit(qs_qureg *q, qs_circuit *c);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,4 +13,7 @@ def __getattr__(name):
     if name == "Qureg":
         from .qureg import Qureg
         return Qureg
+    if name == "Circuit":
+        from .circuit import Circuit
+        return Circuit
     raise AttributeError(name)

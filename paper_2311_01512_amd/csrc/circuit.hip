@@ -1,0 +1,359 @@
+// Recorded circuits: the plain per-gate pass list, or gates fused into dense
+// k-qubit blocks (FP64 products on the host), with every pass's matrix kept
+// on the device in the layout of the kernel that runs it.
+#include "common.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace qs {
+
+struct CircOp {
+    bool gadget;
+    std::vector<int> ctrls, targs;    // unitary: controls, targets in matrix order
+    std::vector<cd> M;                // unitary matrix, row-major 2^nt x 2^nt
+    std::vector<int> paulis;          // gadget: codes per target
+    double theta;
+    std::vector<int> support() const
+    {
+        std::vector<int> s;
+        if (gadget) {
+            for (size_t k = 0; k < targs.size(); k++)
+                if (paulis[k] != 0) s.push_back(targs[k]);
+        } else {
+            s = ctrls;
+            s.insert(s.end(), targs.begin(), targs.end());
+        }
+        return s;
+    }
+};
+
+struct Pass {
+    bool gadget;
+    std::vector<int> ctrls, sorted_targs;
+    std::vector<cd> Ms;               // dense matrix in ascending target order
+    std::vector<int> gtargs, paulis;  // gadget pass
+    double theta;
+    int kernel;
+    size_t dev_offset;                // into the circuit's device buffer
+    bool has_dev;
+    int members;
+};
+
+// Dense matrix of a gadget exp(i theta P) on its non-identity targets, in
+// the order of those targets: cos(theta) 1 + i sin(theta) P, with
+// P[r][c] = prod_q sigma_q[r_q][c_q] (Sec. "Pauli gadget").
+static std::vector<cd> gadget_matrix(const std::vector<int> &codes, double theta)
+{
+    static const cd sig[4][2][2] = {{{1, 0}, {0, 1}},
+                                    {{0, 1}, {1, 0}},
+                                    {{0, cd(0, -1)}, {cd(0, 1), 0}},
+                                    {{1, 0}, {0, -1}}};
+    const int n = (int)codes.size(), D = 1 << n;
+    std::vector<cd> G((size_t)D * D);
+    const double c = std::cos(theta), s = std::sin(theta);
+    for (int r = 0; r < D; r++)
+        for (int col = 0; col < D; col++) {
+            cd p = 1.0;
+            for (int q = 0; q < n; q++) p *= sig[codes[q]][(r >> q) & 1][(col >> q) & 1];
+            G[(size_t)r * D + col] = cd(0, s) * p + (r == col ? cd(c, 0) : cd(0, 0));
+        }
+    return G;
+}
+
+// The op written densely on the block qubits B (ascending; bit p <-> B[p]),
+// controls expanded: identity on columns whose control bits are not all 1.
+static std::vector<cd> embed_in_block(const CircOp &op, const std::vector<int> &B)
+{
+    std::vector<int> targs = op.targs, ctrls = op.ctrls;
+    std::vector<cd> M = op.M;
+    if (op.gadget) {
+        std::vector<int> codes;
+        targs.clear();
+        for (size_t k = 0; k < op.targs.size(); k++)
+            if (op.paulis[k] != 0) {
+                targs.push_back(op.targs[k]);
+                codes.push_back(op.paulis[k]);
+            }
+        M = gadget_matrix(codes, op.theta);
+        ctrls.clear();
+    }
+    auto pos = [&](int qb) { return (int)(std::find(B.begin(), B.end(), qb) - B.begin()); };
+    const int n = (int)B.size(), D = 1 << n, nt = (int)targs.size(), d = 1 << nt;
+    int cmask = 0, tmask = 0;
+    for (int c : ctrls) cmask |= 1 << pos(c);
+    std::vector<int> tp(nt);
+    for (int q = 0; q < nt; q++) {
+        tp[q] = pos(targs[q]);
+        tmask |= 1 << tp[q];
+    }
+    std::vector<cd> E((size_t)D * D, cd(0, 0));
+    for (int col = 0; col < D; col++) {
+        if ((col & cmask) != cmask) {
+            E[(size_t)col * D + col] = 1.0;
+            continue;
+        }
+        int l = 0;
+        for (int q = 0; q < nt; q++) l |= ((col >> tp[q]) & 1) << q;
+        for (int j = 0; j < d; j++) {
+            int row = col & ~tmask;
+            for (int q = 0; q < nt; q++) row |= ((j >> q) & 1) << tp[q];
+            E[(size_t)row * D + col] += M[(size_t)j * d + l];
+        }
+    }
+    return E;
+}
+
+static std::vector<cd> matmul(const std::vector<cd> &A, const std::vector<cd> &B, int D)
+{
+    std::vector<cd> C((size_t)D * D, cd(0, 0));
+    for (int i = 0; i < D; i++)
+        for (int k = 0; k < D; k++) {
+            const cd a = A[(size_t)i * D + k];
+            if (a == cd(0, 0)) continue;
+            for (int j = 0; j < D; j++) C[(size_t)i * D + j] += a * B[(size_t)k * D + j];
+        }
+    return C;
+}
+
+}  // namespace qs
+
+using namespace qs;
+
+struct qs_circuit {
+    int num_qubits;
+    std::vector<CircOp> ops;
+    std::vector<Pass> passes;
+    bool compiled = false;
+    int precision = -1;
+    int fuse_k = 0;
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    int device = -1;
+};
+
+namespace qs {
+
+static Pass single_pass(const CircOp &op)
+{
+    Pass p{};
+    p.members = 1;
+    if (op.gadget) {
+        p.gadget = true;
+        p.gtargs = op.targs;
+        p.paulis = op.paulis;
+        p.theta = op.theta;
+    } else {
+        p.gadget = false;
+        p.ctrls = op.ctrls;
+        p.Ms = permute_to_sorted(op.M, op.targs, p.sorted_targs);
+    }
+    return p;
+}
+
+// Greedy fusion: start a block at the earliest unplaced fusable op and pull
+// in later ops while the qubit set stays within k and the op commutes with
+// every skipped op (no shared qubit).
+static void fuse(qs_circuit *c, int k)
+{
+    const int n_ops = (int)c->ops.size();
+    std::vector<char> placed(n_ops, 0);
+    std::vector<std::vector<int>> sup(n_ops);
+    for (int i = 0; i < n_ops; i++) sup[i] = c->ops[i].support();
+    const int lookahead = 256;
+    for (int i = 0; i < n_ops; i++) {
+        if (placed[i]) continue;
+        placed[i] = 1;
+        if ((int)sup[i].size() > k || sup[i].empty()) {
+            c->passes.push_back(single_pass(c->ops[i]));
+            continue;
+        }
+        std::vector<int> B = sup[i];
+        std::vector<int> members{i};
+        uint64_t blocked = 0;
+        for (int j = i + 1; j < n_ops && j < i + lookahead; j++) {
+            if (placed[j]) continue;
+            uint64_t sj = 0;
+            for (int qb : sup[j]) sj |= 1ULL << qb;
+            if (sj & blocked) {
+                blocked |= sj;
+            } else {
+                std::vector<int> U = B;
+                for (int qb : sup[j])
+                    if (std::find(U.begin(), U.end(), qb) == U.end()) U.push_back(qb);
+                if ((int)U.size() <= k && !sup[j].empty()) {
+                    B = U;
+                    members.push_back(j);
+                    placed[j] = 1;
+                } else {
+                    blocked |= sj;
+                }
+            }
+            if (__builtin_popcountll(blocked) >= c->num_qubits) break;
+        }
+        if (members.size() == 1) {
+            c->passes.push_back(single_pass(c->ops[i]));
+            continue;
+        }
+        std::sort(B.begin(), B.end());
+        const int D = 1 << B.size();
+        std::vector<cd> G((size_t)D * D, cd(0, 0));
+        for (int d = 0; d < D; d++) G[(size_t)d * D + d] = 1.0;
+        for (int m : members) G = matmul(embed_in_block(c->ops[m], B), G, D);
+        Pass p{};
+        p.gadget = false;
+        p.sorted_targs = B;
+        p.Ms = G;
+        p.members = (int)members.size();
+        c->passes.push_back(p);
+    }
+}
+
+}  // namespace qs
+
+extern "C" {
+
+int qs_circuit_create(int num_qubits, qs_circuit **out)
+{
+    if (!out) return fail(QS_E_ARG, "null output pointer");
+    if (num_qubits < 1 || num_qubits > 40) return fail(QS_E_ARG, "qubit count out of range");
+    *out = new (std::nothrow) qs_circuit{};
+    if (!*out) return fail(QS_E_ALLOC, "host allocation failed");
+    (*out)->num_qubits = num_qubits;
+    return QS_OK;
+}
+
+int qs_circuit_destroy(qs_circuit *c)
+{
+    if (!c) return QS_OK;
+    if (c->dev) (void)hipFree(c->dev);
+    delete c;
+    return QS_OK;
+}
+
+int qs_circuit_add_unitary(qs_circuit *c, const int *ctrls, int num_ctrls, const int *targs, int num_targs,
+                           const double *matrix)
+{
+    if (!c || !matrix || !targs || (num_ctrls > 0 && !ctrls)) return fail(QS_E_ARG, "null argument");
+    if (num_targs < 1 || num_targs > 6 || num_ctrls < 0) return fail(QS_E_ARG, "1 to 6 targets supported per gate");
+    std::vector<int> all(ctrls, ctrls + num_ctrls);
+    all.insert(all.end(), targs, targs + num_targs);
+    std::string why;
+    if (!valid_qubits(all.data(), (int)all.size(), c->num_qubits, why)) return fail(QS_E_ARG, why);
+    if ((int)all.size() > kMaxInsert) return fail(QS_E_ARG, "too many controls");
+    CircOp op{};
+    op.gadget = false;
+    op.ctrls.assign(ctrls, ctrls + num_ctrls);
+    op.targs.assign(targs, targs + num_targs);
+    const size_t D = (size_t)1 << num_targs;
+    op.M.resize(D * D);
+    for (size_t i = 0; i < D * D; i++) op.M[i] = cd(matrix[2 * i], matrix[2 * i + 1]);
+    c->ops.push_back(std::move(op));
+    c->compiled = false;
+    return QS_OK;
+}
+
+int qs_circuit_add_pauli_gadget(qs_circuit *c, const int *targs, const int *paulis, int num_targs, double theta)
+{
+    if (!c || !targs || !paulis || num_targs < 1) return fail(QS_E_ARG, "need at least one target");
+    std::string why;
+    if (!valid_qubits(targs, num_targs, c->num_qubits, why)) return fail(QS_E_ARG, why);
+    for (int k = 0; k < num_targs; k++)
+        if (paulis[k] < 0 || paulis[k] > 3) return fail(QS_E_ARG, "Pauli codes are 0..3");
+    CircOp op{};
+    op.gadget = true;
+    op.targs.assign(targs, targs + num_targs);
+    op.paulis.assign(paulis, paulis + num_targs);
+    op.theta = theta;
+    c->ops.push_back(std::move(op));
+    c->compiled = false;
+    return QS_OK;
+}
+
+int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision)
+{
+    if (!c) return fail(QS_E_ARG, "null circuit");
+    if (precision != QS_C64 && precision != QS_C128) return fail(QS_E_ARG, "bad precision");
+    if (fuse_k != 0 && (fuse_k < 2 || fuse_k > 6)) return fail(QS_E_ARG, "fuse_k is 0 or 2..6");
+    c->passes.clear();
+    if (fuse_k == 0) {
+        for (const auto &op : c->ops) c->passes.push_back(single_pass(op));
+    } else {
+        fuse(c, fuse_k);
+    }
+    // device copies of every dense pass's matrix, in its kernel's layout
+    size_t total = 0;
+    for (auto &p : c->passes) {
+        if (p.gadget) continue;
+        const int nt = (int)p.sorted_targs.size();
+        p.kernel = choose_dense_kernel(precision, nt);
+        const size_t b = dense_matrix_bytes(precision, nt, p.kernel);
+        p.has_dev = b > 0;
+        p.dev_offset = total;
+        total += (b + 255) & ~size_t(255);
+    }
+    if (c->dev) {
+        (void)hipFree(c->dev);
+        c->dev = nullptr;
+    }
+    if (total > 0) {
+        std::vector<unsigned char> host(total, 0);
+        for (auto &p : c->passes)
+            if (!p.gadget && p.has_dev)
+                pack_dense(precision, (int)p.sorted_targs.size(), p.kernel, p.Ms, host.data() + p.dev_offset);
+        if (hipMalloc(&c->dev, total) != hipSuccess) {
+            (void)hipGetLastError();
+            c->dev = nullptr;
+            return fail(QS_E_ALLOC, "device allocation of circuit matrices failed");
+        }
+        QS_HIP(hipMemcpy(c->dev, host.data(), total, hipMemcpyHostToDevice));
+        QS_HIP(hipGetDevice(&c->device));
+    }
+    c->dev_bytes = total;
+    c->precision = precision;
+    c->fuse_k = fuse_k;
+    c->compiled = true;
+    return QS_OK;
+}
+
+int qs_circuit_stats(const qs_circuit *c, int *num_ops, int *num_passes, uint64_t *logical_updates,
+                     int *blocks_by_width)
+{
+    if (!c) return fail(QS_E_ARG, "null circuit");
+    if (num_ops) *num_ops = (int)c->ops.size();
+    if (num_passes) *num_passes = c->compiled ? (int)c->passes.size() : -1;
+    if (logical_updates) {
+        uint64_t u = 0;
+        for (const auto &op : c->ops)
+            u += op.gadget ? (1ULL << c->num_qubits) : (1ULL << (c->num_qubits - (int)op.ctrls.size()));
+        *logical_updates = u;
+    }
+    if (blocks_by_width) {
+        for (int i = 0; i < 7; i++) blocks_by_width[i] = 0;
+        for (const auto &p : c->passes) blocks_by_width[p.gadget ? 0 : (int)p.sorted_targs.size()]++;
+    }
+    return QS_OK;
+}
+
+int qs_apply_circuit(qs_qureg *q, qs_circuit *c)
+{
+    if (!q || !c) return fail(QS_E_ARG, "null argument");
+    if (q->is_density) return fail(QS_E_PRECOND, "circuits apply to statevectors");
+    if (q->num_qubits != c->num_qubits) return fail(QS_E_ARG, "qubit counts differ");
+    if (!c->compiled) return fail(QS_E_PRECOND, "circuit is not compiled");
+    if (c->precision != q->precision) return fail(QS_E_TYPE, "circuit compiled for the other precision");
+    if (c->dev && c->device != q->device) return fail(QS_E_PRECOND, "circuit matrices live on another device");
+    for (const auto &p : c->passes) {
+        int rc;
+        if (p.gadget) {
+            rc = apply_raw_gadget(q, p.gtargs, p.paulis, p.theta);
+        } else {
+            const void *dev = p.has_dev ? (const void *)((const unsigned char *)c->dev + p.dev_offset) : nullptr;
+            rc = launch_dense(q, p.ctrls, p.sorted_targs, p.Ms, dev, p.kernel);
+        }
+        if (rc != QS_OK) return rc;
+    }
+    return QS_OK;
+}
+
+}  // extern "C"

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <complex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -140,5 +141,37 @@ int stage_matrix(qs_qureg *q, const void *host, size_t bytes, const void **dev);
 
 // Device reduction helpers, defined in reduce.hip.
 int finish_reduction(qs_qureg *q, int blocks, int width, double *out);
+
+// ---- dense gates (gates.hip) ---------------------------------------------------
+
+using cd = std::complex<double>;
+
+enum { kDenseVector = 0, kDenseMfma = 1 };
+
+// Reorders a matrix whose index bit q belongs to targs[q] into ascending
+// target order; sorted_out receives the sorted targets.
+std::vector<cd> permute_to_sorted(const std::vector<cd> &M, const std::vector<int> &targs,
+                                  std::vector<int> &sorted_out);
+// Device bytes of a dense matrix in a kernel's layout (0: passed by value).
+size_t dense_matrix_bytes(int precision, int nt, int kernel);
+// Writes Ms (ascending target order, FP64) into out in the kernel's layout.
+void pack_dense(int precision, int nt, int kernel, const std::vector<cd> &Ms, void *out);
+// Kernel family used for an nt-target dense gate at a precision.
+int choose_dense_kernel(int precision, int nt);
+// Launches a dense gate whose matrix Ms is in ascending target order; dev is
+// its device copy in the kernel's layout, or null to stage it now.
+int launch_dense(qs_qureg *q, const std::vector<int> &ctrls, const std::vector<int> &sorted_targs,
+                 const std::vector<cd> &Ms, const void *dev, int kernel);
+int apply_raw_gate(qs_qureg *q, const std::vector<int> &ctrls, const std::vector<int> &targs,
+                   const std::vector<cd> &M);
+int apply_raw_gadget(qs_qureg *q, const std::vector<int> &targs, const std::vector<int> &paulis, double theta);
+std::vector<cd> superop_of_kraus(const std::vector<std::vector<cd>> &ks, int n);
+
+// ---- tuning knobs (tune.hip) ---------------------------------------------------
+
+// 1: dense gates of 4-6 targets on complex64 use MFMA, 0: vector FMAs.
+int mfma_preference();
+// Upper bound on the MFMA kernel's grid for a k-target gate.
+uint64_t mfma_block_cap(int k);
 
 }  // namespace qs

@@ -9,7 +9,7 @@
 
 namespace qs {
 
-using cd = std::complex<double>;
+
 
 // Target bit masks of one launch, ascending: tb[p] = 1 << s[p].
 struct TargBits {
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_gadget_diag(C2<R> *__restrict__ a, uint
 
 // Reorders a 2^n x 2^n matrix whose index bit q belongs to targs[q] into one
 // whose index bit p belongs to the p-th smallest target.
-static std::vector<cd> permute_to_sorted(const std::vector<cd> &M, const std::vector<int> &targs,
+std::vector<cd> permute_to_sorted(const std::vector<cd> &M, const std::vector<int> &targs,
                                          std::vector<int> &sorted_out)
 {
     const int n = (int)targs.size();
@@ -148,44 +148,230 @@ static std::vector<cd> permute_to_sorted(const std::vector<cd> &M, const std::ve
     return out;
 }
 
+// ---- FP32 MFMA dense gate (complex64 state) -------------------------------------------
+//
+// The k-target gate as a real GEMM.  With G = Gr + i Gi (D x D, D = 2^k) and
+// a tile X of 16 groups (D x 16 complex), Y = G X is computed as
+//   [Yr; Yi] = [[Gr, -Gi], [Gi, Gr]] [Xr; Xi]
+// by v_mfma_f32_16x16x4f32: M = 2D output rows in 16-row blocks, K = 2D rows
+// of [Xr; Xi] in 4-row steps, N = 16 groups.  Lane L holds group L % 16;
+// for K-step s it holds row 4 s + L / 16 of [Xr; Xi] (the B operand), which
+// is the real (s < D/4) or imaginary part of one amplitude it loaded, and it
+// receives output rows 4 (L / 16) + i of each 16-row block (i = 0..3).  The
+// packed A operands (the big real matrix in MFMA lane order) sit in LDS.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int K>
+__global__ __launch_bounds__(256) void k_dense_mfma(float2 *__restrict__ a, uint64_t num_tiles, InsertPlan plan,
+                                                     uint64_t ctrl_mask, TargBits tb,
+                                                     const f32x4 *__restrict__ apack)
+{
+    constexpr int D = 1 << K;
+    constexpr int KS = 2 * D / 4;    // K-steps
+    constexpr int MB = 2 * D / 16;   // 16-row output blocks
+    constexpr int NA = MB * KS / 4;  // float4 A-operand packs per lane
+    extern __shared__ f32x4 lds_a[];
+    for (int i = threadIdx.x; i < NA * 64; i += blockDim.x) lds_a[i] = apack[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, rq = lane >> 4;
+    // input row 4 s + rq: target bits 0-1 from rq (per lane), bits >= 2 from s
+    const uint64_t off_in = ((rq & 1) ? tb.b[0] : 0) | ((rq & 2) ? tb.b[1] : 0);
+    // output row 16 m + 4 rq + i: target bits 2-3 from rq (per lane)
+    const uint64_t off_out = ((rq & 1) ? tb.b[2] : 0) | ((rq & 2) ? tb.b[3] : 0);
+    const uint64_t num_waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+
+    for (uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave; tile < num_tiles; tile += num_waves) {
+        // keep the LDS operand reads inside the loop (no hoisting into registers)
+        asm volatile("" ::: "memory");
+        const uint64_t base = insert_zeros(tile * 16 + col, plan) | ctrl_mask;
+        float2 x[D / 4];
+#pragma unroll
+        for (int s = 0; s < D / 4; s++) {
+            uint64_t o = off_in;
+#pragma unroll
+            for (int p = 2; p < K; p++)
+                if ((s >> (p - 2)) & 1) o |= tb.b[p];
+            x[s] = a[base | o];
+        }
+        f32x4 acc[MB];
+#pragma unroll
+        for (int m = 0; m < MB; m++) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kq = 0; kq < KS / 4; kq++) {
+#pragma unroll
+            for (int m = 0; m < MB; m++) {
+                const f32x4 av = lds_a[(m * (KS / 4) + kq) * 64 + lane];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int ks = 4 * kq + r;
+                    const float bv = ks < D / 4 ? x[ks].x : x[ks - D / 4].y;
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r], bv, acc[m], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < D / 16; m++) {
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                uint64_t o = off_out | ((i & 1) ? tb.b[0] : 0) | ((i & 2) ? tb.b[1] : 0);
+#pragma unroll
+                for (int p = 4; p < K; p++)
+                    if ((m >> (p - 4)) & 1) o |= tb.b[p];
+                a[base | o] = make_float2(acc[m][i], acc[m + D / 16][i]);
+            }
+        }
+    }
+}
+
+// Packs a D x D complex matrix (sorted target order) into the A-operand
+// order of k_dense_mfma: element r of float4 number (m * KS/4 + kq) * 64 + L
+// is B[16 m + L % 16][4 (4 kq + r) + L / 16] of the real matrix
+// B = [[Gr, -Gi], [Gi, Gr]].
+static void pack_mfma(const std::vector<cd> &Ms, int k, float *out)
+{
+    const int D = 1 << k, KS = 2 * D / 4, MB = 2 * D / 16;
+    auto big = [&](int row, int c) -> double {
+        const cd g = Ms[(size_t)(row % D) * D + (c % D)];
+        const bool rim = row >= D, cim = c >= D;
+        if (!rim && !cim) return g.real();
+        if (!rim && cim) return -g.imag();
+        if (rim && !cim) return g.imag();
+        return g.real();
+    };
+    for (int m = 0; m < MB; m++)
+        for (int kq = 0; kq < KS / 4; kq++)
+            for (int L = 0; L < 64; L++)
+                for (int r = 0; r < 4; r++)
+                    out[(((size_t)m * (KS / 4) + kq) * 64 + L) * 4 + r] =
+                        (float)big(16 * m + (L % 16), 4 * (4 * kq + r) + L / 16);
+}
+
+// ---- dense-gate launch interface ------------------------------------------------------------
+
+size_t dense_matrix_bytes(int precision, int nt, int kernel)
+{
+    const size_t D = (size_t)1 << nt;
+    if (kernel == kDenseMfma) return 4 * D * D * sizeof(float);
+    if (nt <= 2) return 0;                               // passed by value
+    return D * D * (precision == QS_C64 ? sizeof(float2) : sizeof(double2));
+}
+
+void pack_dense(int precision, int nt, int kernel, const std::vector<cd> &Ms, void *out)
+{
+    const size_t D = (size_t)1 << nt;
+    if (kernel == kDenseMfma) {
+        pack_mfma(Ms, nt, (float *)out);
+    } else if (precision == QS_C64) {
+        float2 *o = (float2 *)out;
+        for (size_t i = 0; i < D * D; i++) o[i] = make_float2((float)Ms[i].real(), (float)Ms[i].imag());
+    } else {
+        double2 *o = (double2 *)out;
+        for (size_t i = 0; i < D * D; i++) o[i] = make_double2(Ms[i].real(), Ms[i].imag());
+    }
+}
+
+int choose_dense_kernel(int precision, int nt)
+{
+    const int pref = mfma_preference();
+    if (precision != QS_C64 || nt < 4 || nt > 6) return kDenseVector;
+    if (pref == 0) return kDenseVector;
+    return kDenseMfma;
+}
+
 template <typename R, int NT>
-static int launch_gate_t(qs_qureg *q, uint64_t num_groups, const InsertPlan &plan, uint64_t ctrl_mask,
-                         const TargBits &tb, const std::vector<cd> &M)
+static int launch_vector(qs_qureg *q, uint64_t num_groups, const InsertPlan &plan, uint64_t ctrl_mask,
+                         const TargBits &tb, const std::vector<cd> &Ms, const void *dev)
 {
     constexpr int D = 1 << NT;
     const unsigned grid = grid_for(num_groups, 256);
     if constexpr (NT <= 2) {
         ArgMat<R, NT> am;
-        for (int i = 0; i < D * D; i++) am.m[i] = C2<R>{(R)M[i].real(), (R)M[i].imag()};
+        for (int i = 0; i < D * D; i++) am.m[i] = C2<R>{(R)Ms[i].real(), (R)Ms[i].imag()};
         hipLaunchKernelGGL((k_gate<R, NT, true>), dim3(grid), dim3(256), 0, q->stream, (C2<R> *)q->amps,
                            num_groups, plan, ctrl_mask, tb, am, (const C2<R> *)nullptr);
     } else {
-        std::vector<C2<R>> hm(D * D);
-        for (int i = 0; i < D * D; i++) hm[i] = C2<R>{(R)M[i].real(), (R)M[i].imag()};
-        const void *dm = nullptr;
-        int rc = stage_matrix(q, hm.data(), hm.size() * sizeof(C2<R>), &dm);
-        if (rc != QS_OK) return rc;
+        if (!dev) {
+            std::vector<C2<R>> hm(D * D);
+            pack_dense(q->precision, NT, kDenseVector, Ms, hm.data());
+            int rc = stage_matrix(q, hm.data(), hm.size() * sizeof(C2<R>), &dev);
+            if (rc != QS_OK) return rc;
+        }
         ArgMat<R, 1> dummy{};
         hipLaunchKernelGGL((k_gate<R, NT, false>), dim3(grid), dim3(256), D * D * sizeof(C2<R>), q->stream,
-                           (C2<R> *)q->amps, num_groups, plan, ctrl_mask, tb, dummy, (const C2<R> *)dm);
+                           (C2<R> *)q->amps, num_groups, plan, ctrl_mask, tb, dummy, (const C2<R> *)dev);
     }
     QS_LAUNCH_CHECK();
     return QS_OK;
 }
 
+template <int K>
+static int launch_mfma(qs_qureg *q, uint64_t num_groups, const InsertPlan &plan, uint64_t ctrl_mask,
+                       const TargBits &tb, const std::vector<cd> &Ms, const void *dev)
+{
+    constexpr int D = 1 << K;
+    const size_t bytes = 4 * (size_t)D * D * sizeof(float);
+    if (!dev) {
+        std::vector<float> hm(4 * D * D);
+        pack_mfma(Ms, K, hm.data());
+        int rc = stage_matrix(q, hm.data(), bytes, &dev);
+        if (rc != QS_OK) return rc;
+    }
+    const uint64_t tiles = num_groups / 16;   // num_groups is a multiple of 16 (checked by the caller)
+    const uint64_t waves_per_block = 4;
+    uint64_t blocks = (tiles + waves_per_block - 1) / waves_per_block;
+    const uint64_t cap = mfma_block_cap(K);
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL((k_dense_mfma<K>), dim3((unsigned)blocks), dim3(256), bytes, q->stream, (float2 *)q->amps,
+                       tiles, plan, ctrl_mask, tb, (const f32x4 *)dev);
+    QS_LAUNCH_CHECK();
+    return QS_OK;
+}
+
 template <typename R>
-static int launch_gate_r(qs_qureg *q, int nt, uint64_t num_groups, const InsertPlan &plan, uint64_t ctrl_mask,
-                         const TargBits &tb, const std::vector<cd> &M)
+static int launch_vector_r(qs_qureg *q, int nt, uint64_t num_groups, const InsertPlan &plan, uint64_t ctrl_mask,
+                           const TargBits &tb, const std::vector<cd> &Ms, const void *dev)
 {
     switch (nt) {
-    case 1: return launch_gate_t<R, 1>(q, num_groups, plan, ctrl_mask, tb, M);
-    case 2: return launch_gate_t<R, 2>(q, num_groups, plan, ctrl_mask, tb, M);
-    case 3: return launch_gate_t<R, 3>(q, num_groups, plan, ctrl_mask, tb, M);
-    case 4: return launch_gate_t<R, 4>(q, num_groups, plan, ctrl_mask, tb, M);
-    case 5: return launch_gate_t<R, 5>(q, num_groups, plan, ctrl_mask, tb, M);
-    case 6: return launch_gate_t<R, 6>(q, num_groups, plan, ctrl_mask, tb, M);
+    case 1: return launch_vector<R, 1>(q, num_groups, plan, ctrl_mask, tb, Ms, dev);
+    case 2: return launch_vector<R, 2>(q, num_groups, plan, ctrl_mask, tb, Ms, dev);
+    case 3: return launch_vector<R, 3>(q, num_groups, plan, ctrl_mask, tb, Ms, dev);
+    case 4: return launch_vector<R, 4>(q, num_groups, plan, ctrl_mask, tb, Ms, dev);
+    case 5: return launch_vector<R, 5>(q, num_groups, plan, ctrl_mask, tb, Ms, dev);
+    case 6: return launch_vector<R, 6>(q, num_groups, plan, ctrl_mask, tb, Ms, dev);
     default: return fail(QS_E_ARG, "1 to 6 targets supported per gate");
     }
+}
+
+int launch_dense(qs_qureg *q, const std::vector<int> &ctrls, const std::vector<int> &sorted_targs,
+                 const std::vector<cd> &Ms, const void *dev, int kernel)
+{
+    const int nt = (int)sorted_targs.size(), nc = (int)ctrls.size();
+    if (nt < 1 || nt > 6) return fail(QS_E_ARG, "1 to 6 targets supported per gate");
+    if (nc + nt > q->index_bits) return fail(QS_E_ARG, "more controls and targets than qubits");
+    if (nc + nt > kMaxInsert) return fail(QS_E_ARG, "too many controls");
+    std::vector<int> all(ctrls);
+    all.insert(all.end(), sorted_targs.begin(), sorted_targs.end());
+    InsertPlan plan = make_insert_plan(all);
+    uint64_t ctrl_mask = 0;
+    for (int c : ctrls) ctrl_mask |= 1ULL << c;
+    TargBits tb{};
+    for (int p = 0; p < nt; p++) tb.b[p] = 1ULL << sorted_targs[p];
+    const uint64_t num_groups = 1ULL << (q->index_bits - nc - nt);
+    if (kernel == kDenseMfma && (q->precision != QS_C64 || nt < 4 || num_groups < 16)) {
+        kernel = kDenseVector;
+        dev = nullptr;   // a device copy in the MFMA layout does not fit the vector kernel
+    }
+    if (kernel == kDenseMfma) {
+        switch (nt) {
+        case 4: return launch_mfma<4>(q, num_groups, plan, ctrl_mask, tb, Ms, dev);
+        case 5: return launch_mfma<5>(q, num_groups, plan, ctrl_mask, tb, Ms, dev);
+        default: return launch_mfma<6>(q, num_groups, plan, ctrl_mask, tb, Ms, dev);
+        }
+    }
+    return q->precision == QS_C64 ? launch_vector_r<float>(q, nt, num_groups, plan, ctrl_mask, tb, Ms, dev)
+                                  : launch_vector_r<double>(q, nt, num_groups, plan, ctrl_mask, tb, Ms, dev);
 }
 
 // Gate on the raw amplitude array viewed as index_bits qubits (a statevector,
@@ -193,22 +379,10 @@ static int launch_gate_r(qs_qureg *q, int nt, uint64_t num_groups, const InsertP
 int apply_raw_gate(qs_qureg *q, const std::vector<int> &ctrls, const std::vector<int> &targs,
                    const std::vector<cd> &M)
 {
-    const int nt = (int)targs.size(), nc = (int)ctrls.size();
-    if (nt < 1 || nt > 6) return fail(QS_E_ARG, "1 to 6 targets supported per gate");
-    if (nc + nt > q->index_bits) return fail(QS_E_ARG, "more controls and targets than qubits");
-    if (nc + nt > kMaxInsert) return fail(QS_E_ARG, "too many controls");
     std::vector<int> sorted;
     std::vector<cd> Ms = permute_to_sorted(M, targs, sorted);
-    std::vector<int> all(ctrls);
-    all.insert(all.end(), targs.begin(), targs.end());
-    InsertPlan plan = make_insert_plan(all);
-    uint64_t ctrl_mask = 0;
-    for (int c : ctrls) ctrl_mask |= 1ULL << c;
-    TargBits tb{};
-    for (int p = 0; p < nt; p++) tb.b[p] = 1ULL << sorted[p];
-    const uint64_t num_groups = 1ULL << (q->index_bits - nc - nt);
-    return q->precision == QS_C64 ? launch_gate_r<float>(q, nt, num_groups, plan, ctrl_mask, tb, Ms)
-                                  : launch_gate_r<double>(q, nt, num_groups, plan, ctrl_mask, tb, Ms);
+    const int nt = (int)targs.size();
+    return launch_dense(q, ctrls, sorted, Ms, nullptr, choose_dense_kernel(q->precision, nt));
 }
 
 // Pauli gadget on the raw array (index_bits qubits).

@@ -12,7 +12,7 @@
 
 namespace qs {
 
-using cd = std::complex<double>;
+
 
 __device__ __forceinline__ double wave_sum(double v)
 {

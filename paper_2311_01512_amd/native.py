@@ -63,6 +63,13 @@ _SIGS = {
     "qs_calc_trace": [_P, _PD, _PD],
     "qs_calc_purity": [_P, _PD, _PD],
     "qs_calc_inner_product": [_P, _P, _PD, _PD],
+    "qs_circuit_create": [_I, _PP],
+    "qs_circuit_destroy": [_P],
+    "qs_circuit_add_unitary": [_P, _P, _I, _P, _I, _P],
+    "qs_circuit_add_pauli_gadget": [_P, _P, _P, _I, _D],
+    "qs_circuit_compile": [_P, _I, _I],
+    "qs_circuit_stats": [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_uint64), C.POINTER(C.c_int)],
+    "qs_apply_circuit": [_P, _P],
 }
 
 for _name, _args in _SIGS.items():
@@ -232,3 +239,45 @@ def qs_calc_inner_product(a, b):
     re, im = C.c_double(), C.c_double()
     check(lib.qs_calc_inner_product(a, b, C.byref(re), C.byref(im)), "qs_calc_inner_product")
     return complex(re.value, im.value)
+
+
+# ---- circuits ------------------------------------------------------------------
+
+def qs_circuit_create(num_qubits):
+    out = C.c_void_p()
+    check(lib.qs_circuit_create(num_qubits, C.byref(out)), "qs_circuit_create")
+    return out
+
+
+def qs_circuit_destroy(c):
+    check(lib.qs_circuit_destroy(c), "qs_circuit_destroy")
+
+
+def qs_circuit_add_unitary(c, ctrls, targs, matrix):
+    cc, t = ints(ctrls), ints(targs)
+    _square(matrix, 1 << t.size, "matrix")
+    m = cmatrix(matrix)
+    check(lib.qs_circuit_add_unitary(c, ptr(cc), cc.size, ptr(t), t.size, ptr(m)), "qs_circuit_add_unitary")
+
+
+def qs_circuit_add_pauli_gadget(c, targs, paulis, theta):
+    t, p = ints(targs), ints(paulis)
+    if t.size != p.size:
+        raise ValueError("targs and paulis differ in length")
+    check(lib.qs_circuit_add_pauli_gadget(c, ptr(t), ptr(p), t.size, float(theta)), "qs_circuit_add_pauli_gadget")
+
+
+def qs_circuit_compile(c, fuse_k, precision):
+    check(lib.qs_circuit_compile(c, fuse_k, precision), "qs_circuit_compile")
+
+
+def qs_circuit_stats(c):
+    no, npass, lu = C.c_int(), C.c_int(), C.c_uint64()
+    widths = (C.c_int * 7)()
+    check(lib.qs_circuit_stats(c, C.byref(no), C.byref(npass), C.byref(lu), widths), "qs_circuit_stats")
+    return {"num_ops": no.value, "num_passes": npass.value, "logical_updates": lu.value,
+            "passes_by_width": list(widths)}
+
+
+def qs_apply_circuit(q, c):
+    check(lib.qs_apply_circuit(q, c), "qs_apply_circuit")

@@ -1,0 +1,131 @@
+"""Parity of the FP32-MFMA dense kernel and of fused circuits (dense k-qubit
+blocks built in FP64) with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import TOL, amp_err, banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qs():
+    import paper_2311_01512_amd as pkg
+    return pkg
+
+
+DENSE_CASES = [
+    # (N, targets, controls): low, high, mixed target sets, with and without controls
+    (8, [0, 1, 2, 3], []), (9, [3, 0, 8, 5], []), (12, [11, 10, 9, 8, 7], []), (12, [0, 5, 1, 9, 3], [11]),
+    (13, [2, 4, 6, 8, 10, 12], []), (14, [0, 1, 2, 3, 4, 5], [13, 7]), (15, [14, 0, 7, 3, 11, 5], [1, 2, 9]),
+    (16, [6, 7, 8, 9], [0, 1, 2, 3]), (5, [0, 1, 2, 3], []), (6, [5, 4, 3, 2, 1], [0]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(DENSE_CASES)))
+def test_mfma_dense_gate_parity(qs, case):
+    N, t, c = DENSE_CASES[case]
+    banner(f"mfma dense N={N} t={t} c={c}")
+    rng = np.random.default_rng(7000 + case)
+    M = synth.haar_unitary(rng, 1 << len(t))
+    psi = synth.random_state(rng, 1 << N)
+    q = qs.Qureg(N, precision="c64").set_amps(psi)
+    q.apply_unitary(c, t, M)
+    want = oracle.apply_gate(psi.copy(), c, t, M)
+    assert amp_err(q.get_amps(), want) < TOL["c64"]
+
+
+def test_mfma_nonunitary_many_tiles(qs):
+    """A general matrix on 6 targets of 18 qubits (4096 tiles of 16 groups)."""
+    rng = np.random.default_rng(7100)
+    N, t = 18, [17, 2, 9, 0, 13, 5]
+    M = synth.random_matrix(rng, 64) / 8
+    psi = synth.random_state(rng, 1 << N)
+    q = qs.Qureg(N, precision="c64").set_amps(psi)
+    q.apply_unitary([], t, M)
+    assert amp_err(q.get_amps(), oracle.apply_gate(psi.copy(), [], t, M)) < TOL["c64"]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("k", [0, 2, 3, 4, 5, 6])
+def test_fused_circuit_parity(qs, prec, k):
+    banner(f"fused circuit k={k} {prec}")
+    N = 14
+    ops = synth.config2_circuit(num_qubits=N, num_gates=300)
+    rng = np.random.default_rng(3)
+    psi = synth.random_state(rng, 1 << N)
+    circ = qs.Circuit(N, ops).compile(k, prec)
+    st = circ.stats()
+    assert st["num_ops"] == len(ops)
+    assert st["logical_updates"] == synth.count_logical_updates(ops, N)
+    if k == 0:
+        assert st["num_passes"] == len(ops)
+    else:
+        assert st["num_passes"] < len(ops)
+        assert max(i for i, w in enumerate(st["passes_by_width"]) if w) <= k
+    q = qs.Qureg(N, precision=prec).set_amps(psi)
+    circ.apply(q)
+    want = oracle.run_ops(psi.copy(), ops)
+    assert amp_err(q.get_amps(), want) < TOL[prec]
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_fusion_respects_order(qs, k):
+    """Dense non-commuting gates on overlapping qubits, interleaved with gates
+    elsewhere: blocks may only absorb ops that commute with what they skip."""
+    rng = np.random.default_rng(11 + k)
+    N = 8
+    ops = []
+    for g in range(120):
+        a = int(rng.integers(0, N))
+        b = (a + int(rng.integers(1, 3))) % N
+        if g % 3 == 0:
+            ops.append({"op": "unitary", "ctrls": (), "targs": (a, b), "matrix": synth.random_matrix(rng, 4) / 2})
+        elif g % 3 == 1:
+            ops.append({"op": "unitary", "ctrls": (b,), "targs": (a,), "matrix": synth.random_matrix(rng, 2)})
+        else:
+            w = int(rng.integers(1, 4))
+            qs_ = rng.permutation(N)[:w]
+            ops.append({"op": "gadget", "targs": tuple(int(x) for x in qs_),
+                        "paulis": tuple(int(x) for x in rng.integers(0, 4, size=w)), "theta": rng.uniform(-3, 3)})
+    psi = synth.random_state(rng, 1 << N)
+    want = oracle.run_ops(psi.copy(), ops)
+    circ = qs.Circuit(N, ops).compile(k, "c128")
+    q = qs.Qureg(N, precision="c128").set_amps(psi)
+    circ.apply(q)
+    # non-unitary factors grow the norm; compare relative to the largest amplitude
+    assert amp_err(q.get_amps(), want) < 1e-10
+
+
+def test_config5_fused_reduced(qs):
+    """The 34-qubit generator at 14 qubits: 5-target gates with up to 4
+    controls and heavy gadgets, fused with k = 6 in complex64."""
+    banner("config5 fused N=14")
+    N = 14
+    ops = synth.config5_circuit(num_qubits=N)
+    rng = np.random.default_rng(5)
+    psi = synth.random_state(rng, 1 << N)
+    circ = qs.Circuit(N, ops).compile(6, "c64")
+    q = qs.Qureg(N, precision="c64").set_amps(psi)
+    circ.apply(q)
+    want = oracle.run_ops(psi.copy(), ops)
+    assert amp_err(q.get_amps(), want) < TOL["c64"]
+
+
+def test_circuit_errors(qs):
+    c = qs.Circuit(4)
+    with pytest.raises(ValueError):
+        c.add({"op": "unitary", "ctrls": (0,), "targs": (0,), "matrix": np.eye(2)})
+    with pytest.raises(ValueError):
+        c.add({"op": "kraus", "targs": (0,), "kraus": np.eye(2)[None]})
+    c.add({"op": "unitary", "ctrls": (), "targs": (1,), "matrix": np.eye(2)})
+    q = qs.Qureg(4, precision="c64").init_zero()
+    with pytest.raises(ValueError):
+        c.apply(q)                                   # not compiled
+    c.compile(0, "c128")
+    with pytest.raises(TypeError):
+        c.apply(q)                                   # compiled for the other precision
+    with pytest.raises(ValueError):
+        c.compile(7, "c64")
