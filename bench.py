@@ -1,14 +1,20 @@
 """Throughput of the 28-qubit random-circuit workload on one MI355X.
 
-A step is one pass of the 500-gate circuit (Haar 1-qubit gates, 2-target Haar
-gates with 0-3 controls, Pauli gadgets of weight 1-28) over the 2^28-amplitude
-state resident in HBM.  The plain per-gate path runs in complex128, the
-fused path in complex64; both are timed, and the complex64 result is compared
-with the complex128 one amplitude by amplitude.
+A step is one application of the 500-gate circuit (Haar 1-qubit gates,
+2-target Haar gates with 0-3 controls, Pauli gadgets exp(i theta P) of weight
+1-28) to a 2^28-amplitude statevector resident in HBM.  Two paths are timed:
 
-Prints one JSON line.  `value` is logical amplitude-updates/s of the
-headline path (plain per-gate accounting: 2^(N-s) per s-controlled gate, 2^N
-per gadget), with the state already in HBM.
+* fused: complex64 state, gates fused into dense k-qubit blocks (FP64
+  products), blocks of 4-6 qubits run as FP32 MFMA GEMMs; k is picked by the
+  library's autotuner.  This is the headline `value`.
+* plain: complex128 state, one pass per gate (the paper's per-gate method).
+
+`value` is logical amplitude-updates/s (plain per-gate accounting: 2^(N-s)
+per s-controlled gate, 2^N per gadget, credited alike to both paths).  The
+fused complex64 state is compared amplitude by amplitude with the complex128
+one after the same number of circuit applications from the same state.
+
+Prints one JSON line.
 """
 import argparse
 import json
@@ -16,12 +22,11 @@ import os
 import sys
 import time
 
-import numpy as np
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_F32_PEAK_TFLOPS = 157.3
 
 
 def parse():
@@ -31,42 +36,32 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=28)
     ap.add_argument("--gates", type=int, default=500)
+    ap.add_argument("--fuse-candidates", default="0,3,4,5,6")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for hardware-counter collection: one torch copy of 2 GiB "
-                         "(the calibration kernel of known traffic), then one pass of the circuit")
+                         "(the calibration kernel of known traffic), then one application of the "
+                         "fused complex64 circuit")
+    ap.add_argument("--probe-fuse-k", type=int, default=5)
     return ap.parse_args()
 
 
-def pmc_probe(args):
-    import torch
-    import synth
-    import paper_2311_01512_amd as qs
-    n = args.qubits
-    src = torch.zeros(1 << 28, dtype=torch.complex64, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)                      # reads 2 GiB, writes 2 GiB
-    torch.cuda.synchronize()
-    del src, dst
-    ops = synth.config2_circuit(num_qubits=n, num_gates=args.gates)
-    q = qs.Qureg(n, precision="c128").init_hashed(11)
-    q.run_ops(ops)
-    q.sync()
-    print(json.dumps({"pmc_probe": "done", "gates": len(ops), "num_qubits": n}), flush=True)
-
-
-def op_kind(op, real):
-    """Name of the kernel that carries an op on the per-gate path."""
-    if op["op"] == "gadget":
-        xy = any(p in (1, 2) for p in op["paulis"])
-        return f"k_gadget_pairs<{real}>" if xy else f"k_gadget_diag<{real}>"
-    return f"k_gate<{real}, {len(op['targs'])}>"
+def kernel_name(info, real):
+    k = info["kernel"]
+    if k == "gadget_pairs":
+        return f"k_gadget_pairs<{real}>"
+    if k == "gadget_diag":
+        return f"k_gadget_diag<{real}>"
+    if k == "dense_mfma":
+        return f"k_dense_mfma<{info['num_targs']}>"
+    return f"k_gate<{real}, {info['num_targs']}>"
 
 
 def measured_traffic(kernel, n):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when none exists or the kernel source changed since."""
+    summary (profiles/traffic.json), or None when there is none or the
+    kernel's source changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -80,38 +75,64 @@ def measured_traffic(kernel, n):
     return rec["bytes_per_launch"]
 
 
-def op_updates(op, n):
-    if op["op"] == "gadget":
-        return 1 << n
-    return 1 << (n - len(op["ctrls"]))
-
-
-def time_path(q, ops, steps, warmup, torch):
-    """Runs the circuit warmup + steps times; returns (seconds per step,
-    per-kind [launches, total ms]) with per-op HIP events on the qureg's stream."""
-    stream = q.stream
-    for _ in range(warmup):
-        q.run_ops(ops)
+def time_steps(circ, q, steps, torch):
+    """Seconds per application, HIP events on the qureg's stream."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in ops]
-    per_kind = {}
-    total = 0.0
+    a.record(q.stream)
     for _ in range(steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for op, (a, b) in zip(ops, ev):
-            a.record(stream)
-            q.run_ops([op])
-            b.record(stream)
-        torch.cuda.synchronize()
-        total += time.perf_counter() - t0
-        for op, (a, b) in zip(ops, ev):
-            k = op_kind(op, "double" if q.precision == "c128" else "float")
-            c = per_kind.setdefault(k, [0, 0.0, 0])
-            c[0] += 1
-            c[1] += a.elapsed_time(b)
-            c[2] += op_updates(op, q.num_qubits)
-    return total / steps, per_kind
+        circ.apply(q)
+    b.record(q.stream)
+    b.synchronize()
+    return a.elapsed_time(b) * 1e-3 / steps
+
+
+def time_passes(circ, q, torch):
+    """One application pass by pass, each bracketed by HIP events; returns
+    kernel -> [launches, total ms, amplitudes touched, flops]."""
+    n = q.num_qubits
+    real = "float" if q.precision == "c64" else "double"
+    npass = circ.stats()["num_passes"]
+    infos = [circ.pass_info(i) for i in range(npass)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in infos]
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(ev):
+        a.record(q.stream)
+        circ.apply_passes(q, i, 1)
+        b.record(q.stream)
+    torch.cuda.synchronize()
+    out = {}
+    for info, (a, b) in zip(infos, ev):
+        name = kernel_name(info, real)
+        amps = 1 << (n - info["num_ctrls"])
+        flops = 8 * (1 << info["num_targs"]) * amps if info["kernel"].startswith("dense") else 0
+        c = out.setdefault(name, [0, 0.0, 0, 0])
+        c[0] += 1
+        c[1] += a.elapsed_time(b)
+        c[2] += amps
+        c[3] += flops
+    return out
+
+
+def per_kernel_table(kinds, amp_bytes):
+    return {k: {"launches": v[0], "avg_ms": v[1] / v[0],
+                "GBps": 2 * amp_bytes * v[2] / (v[1] * 1e-3) / 1e9,
+                "TFLOPs": (v[3] / (v[1] * 1e-3) / 1e12) if v[3] else None} for k, v in kinds.items()}
+
+
+def roofline(kinds, amp_bytes, n):
+    name, (launches, ms, amps, flops) = max(kinds.items(), key=lambda kv: kv[1][1])
+    avg_s = ms * 1e-3 / launches
+    if name.startswith("k_dense_mfma<6>"):
+        achieved = flops / launches / avg_s / 1e12
+        return {"bound": "mfma", "achieved": achieved, "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / MFMA_F32_PEAK_TFLOPS, "traffic": measured_traffic(name, n),
+                "kernel": name, "avg_launch_ms": avg_s * 1e3, "flops_per_launch": flops / launches}
+    bytes_per_launch = 2 * amp_bytes * amps / launches
+    achieved = bytes_per_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, n),
+            "kernel": name, "avg_launch_ms": avg_s * 1e3, "bytes_per_launch": bytes_per_launch}
 
 
 def cpu_baseline(ops, n, budget_s):
@@ -122,14 +143,33 @@ def cpu_baseline(ops, n, budget_s):
     for op in ops:
         oracle.run_ops(psi, [op])
         done += 1
-        updates += op_updates(op, n)
+        updates += (1 << n) if op["op"] == "gadget" else (1 << (n - len(op["ctrls"])))
         if time.perf_counter() - t0 > budget_s and done >= 2:
             break
     dt = time.perf_counter() - t0
     return {"value": updates / dt, "unit": "amplitude-updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"first {done} of {len(ops)} gates of the {n}-qubit circuit, complex128, "
-                      f"{dt:.1f} s"}
+            "sample": f"first {done} of {len(ops)} gates of the {n}-qubit circuit, plain per-gate "
+                      f"complex128, {dt:.1f} s"}
+
+
+def pmc_probe(args):
+    import torch
+    import synth
+    import paper_2311_01512_amd as qs
+    n = args.qubits
+    src = torch.zeros(1 << 28, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)                      # reads 2 GiB, writes 2 GiB
+    torch.cuda.synchronize()
+    del src, dst
+    ops = synth.config2_circuit(num_qubits=n, num_gates=args.gates)
+    q = qs.Qureg(n, precision="c64").init_hashed(11)
+    circ = qs.Circuit(n, ops).compile(args.probe_fuse_k, "c64")
+    circ.apply(q)
+    q.sync()
+    print(json.dumps({"pmc_probe": "done", "gates": len(ops), "num_qubits": n,
+                      "fuse_k": args.probe_fuse_k}), flush=True)
 
 
 def main():
@@ -148,55 +188,56 @@ def main():
     ops = synth.config2_circuit(num_qubits=n, num_gates=args.gates)
     logical = synth.count_logical_updates(ops, n)
 
-    # plain per-gate path, complex128
-    q128 = qs.Qureg(n, precision="c128").init_hashed(seed)
-    t128, kinds128 = time_path(q128, ops, args.steps, args.warmup, torch)
-    # complex64 path (per-gate until fused blocks are enabled)
+    # fused complex64: autotune the fusion width on a scratch run
     q64 = qs.Qureg(n, precision="c64").init_hashed(seed)
-    t64, kinds64 = time_path(q64, ops, args.steps, args.warmup, torch)
+    fused = qs.Circuit(n, ops)
+    cands = tuple(int(x) for x in args.fuse_candidates.split(","))
+    best_k, tune_ms = fused.autotune(q64, cands)
+    # plain complex128, one pass per gate
+    plain = qs.Circuit(n, ops).compile(0, "c128")
+    q128 = qs.Qureg(n, precision="c128")
 
-    # amplitude error of the complex64 result against the complex128 one,
-    # both after warmup + steps passes of the circuit from the same state
+    q64.init_hashed(seed)
+    q128.init_hashed(seed)
+    for _ in range(args.warmup):
+        fused.apply(q64)
+        plain.apply(q128)
+    t64 = time_steps(fused, q64, args.steps, torch)
+    t128 = time_steps(plain, q128, args.steps, torch)
+    kinds64 = time_passes(fused, q64, torch)
+    kinds128 = time_passes(plain, q128, torch)
+
     with torch.no_grad():
         ref = q128.tensor
-        diff = (q64.tensor.to(torch.complex128) - ref).abs().max().item()
-        err = diff / ref.abs().max().item()
-    del q64
+        err = ((q64.tensor.to(torch.complex128) - ref).abs().max() / ref.abs().max()).item()
 
-    # dominant kernel of the headline path: the kind with the most time
-    head_t, head_kinds, b = t128, kinds128, 16
-    dom = max(head_kinds.items(), key=lambda kv: kv[1][1])
-    k_name, (launches, ms_total, upd) = dom
-    avg_ms = ms_total / launches
-    bytes_per_launch = 2 * b * upd / launches
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-
+    st = fused.stats()
     result = {
         "metric": "amplitude-updates/s & %HBM peak; fused FP32 vs plain FP64 at <=1e-5 amp err",
-        "value": logical / head_t,
+        "value": logical / t64,
         "unit": "amplitude-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": head_t * 1e3,
+        "ms_per_step": t64 * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128 (f64)",
+        "dtype": "c64 (f32)",
         "data": "synthetic seeded random circuit (PCG64), counter-hashed initial state",
-        "config": {"workload": f"{n}-qubit statevector, {len(ops)}-gate random circuit "
-                               "(Haar 1q, 2-target Haar with 0-3 controls, Pauli gadgets weight 1-N)",
-                   "num_qubits": n, "gates": len(ops), "path": "plain per-gate complex128"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(k_name, n),
-                     "kernel": k_name, "avg_launch_ms": avg_ms, "bytes_per_launch": bytes_per_launch},
-        "plain_c128": {"value": logical / t128, "ms_per_step": t128 * 1e3,
-                       "per_kind": {k: {"launches": v[0], "avg_ms": v[1] / v[0],
-                                        "GBps": 2 * 16 * v[2] / (v[1] * 1e-3) / 1e9} for k, v in kinds128.items()}},
-        "c64": {"value": logical / t64, "ms_per_step": t64 * 1e3, "path": "per-gate complex64",
-                "per_kind": {k: {"launches": v[0], "avg_ms": v[1] / v[0],
-                                 "GBps": 2 * 8 * v[2] / (v[1] * 1e-3) / 1e9} for k, v in kinds64.items()},
-                "max_amp_err_vs_c128": err, "speedup_vs_c128": t128 / t64},
+        "config": {"workload": f"{n}-qubit statevector, {len(ops)}-gate random circuit (Haar 1q, "
+                               "2-target Haar with 0-3 controls, Pauli gadgets of weight 1-N)",
+                   "num_qubits": n, "gates": len(ops),
+                   "path": f"complex64, gates fused into dense blocks of <= {best_k} qubits (autotuned), "
+                           "FP32 MFMA for 4-6 qubit blocks"},
+        "roofline": roofline(kinds64, 8, n),
+        "fused_c64": {"value": logical / t64, "ms_per_step": t64 * 1e3, "fuse_k": best_k,
+                      "autotune_ms": {str(k): v for k, v in tune_ms.items()},
+                      "passes": st["num_passes"], "passes_by_width": st["passes_by_width"],
+                      "max_amp_err_vs_c128": err, "per_kernel": per_kernel_table(kinds64, 8)},
+        "plain_c128": {"value": logical / t128, "ms_per_step": t128 * 1e3, "passes": len(ops),
+                       "roofline": roofline(kinds128, 16, n), "per_kernel": per_kernel_table(kinds128, 16)},
+        "speedup_fused_c64_vs_plain_c128": t128 / t64,
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_seconds)

@@ -233,6 +233,29 @@ int qs_circuit_stats(const qs_circuit *c, int *num_ops, int *num_passes, uint64_
  * compiled precision, in order, on the qureg's stream. */
 int qs_apply_circuit(qs_qureg *q, qs_circuit *c);
 
+/* Applies passes [first, first + count) of the compiled circuit (same rules
+ * as qs_apply_circuit); lets a caller time passes one by one. */
+int qs_apply_circuit_passes(qs_qureg *q, qs_circuit *c, int first, int count);
+
+/* Describes pass `index` of the compiled circuit: kernel = 0 Pauli-gadget
+ * pairs, 1 phase gadget (diagonal), 2 dense gate on vector FMAs, 3 dense
+ * gate on FP32 MFMA; num_targs / num_ctrls of a dense pass (gadget: its
+ * Pauli count, 0); members = recorded ops merged into the pass. */
+int qs_circuit_pass_info(const qs_circuit *c, int index, int *kernel, int *num_targs, int *num_ctrls,
+                         int *members);
+
+/*
+ * Autotuner of the fusion width: compiles the circuit for each candidate k
+ * (0 = plain per-gate), applies it to q once untimed and once timed with HIP
+ * events on q's stream, and leaves the circuit compiled with the fastest k.
+ * q's state is overwritten by these runs.  The choice is cached per (qubit
+ * count, precision, circuit contents) for the process, and appended to the
+ * file named by QS_TUNE_CACHE when that variable is set (and read from it
+ * first).  ms_out (may be NULL) receives num_candidates timings in ms.
+ */
+int qs_circuit_autotune(qs_qureg *q, qs_circuit *c, const int *candidates, int num_candidates, int *best_k,
+                        double *ms_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,6 +34,21 @@ class Circuit:
         N.qs_apply_circuit(qureg.handle, self._c)
         return qureg
 
+    def apply_passes(self, qureg, first, count):
+        N.qs_apply_circuit_passes(qureg.handle, self._c, first, count)
+        return qureg
+
+    def pass_info(self, index):
+        return N.qs_circuit_pass_info(self._c, index)
+
+    def autotune(self, qureg, candidates=(0, 3, 4, 5, 6)):
+        """Times one application per fusion width on `qureg` (overwriting its
+        state) and leaves the circuit compiled with the fastest; returns
+        (best_k, {k: ms})."""
+        best, ms = N.qs_circuit_autotune(qureg.handle, self._c, candidates)
+        self.compiled_for = (best, qureg.precision)
+        return best, dict(zip(candidates, ms.tolist()))
+
     def close(self):
         if getattr(self, "_c", None) is not None:
             N.qs_circuit_destroy(self._c)

@@ -337,13 +337,85 @@ int qs_circuit_stats(const qs_circuit *c, int *num_ops, int *num_passes, uint64_
 
 int qs_apply_circuit(qs_qureg *q, qs_circuit *c)
 {
+    if (!c) return fail(QS_E_ARG, "null circuit");
+    return qs_apply_circuit_passes(q, c, 0, (int)c->passes.size());
+}
+
+}  // extern "C"
+
+namespace qs {
+
+// FNV-1a over the recorded ops (structure and matrix bits): the key under
+// which the autotuner caches its choice for a circuit.
+uint64_t circuit_fingerprint(const qs_circuit *c)
+{
+    uint64_t h = 1469598103934665603ULL;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *b = (const unsigned char *)p;
+        for (size_t i = 0; i < n; i++) {
+            h ^= b[i];
+            h *= 1099511628211ULL;
+        }
+    };
+    mix(&c->num_qubits, sizeof(int));
+    for (const auto &op : c->ops) {
+        mix(&op.gadget, sizeof(bool));
+        for (int x : op.ctrls) mix(&x, sizeof(int));
+        for (int x : op.targs) mix(&x, sizeof(int));
+        for (int x : op.paulis) mix(&x, sizeof(int));
+        mix(&op.theta, sizeof(double));
+        if (!op.M.empty()) mix(op.M.data(), op.M.size() * sizeof(cd));
+    }
+    return h;
+}
+
+int circuit_num_qubits(const qs_circuit *c) { return c->num_qubits; }
+
+}  // namespace qs
+
+extern "C" {
+
+int qs_circuit_pass_info(const qs_circuit *c, int index, int *kernel, int *num_targs, int *num_ctrls, int *members)
+{
+    if (!c) return fail(QS_E_ARG, "null circuit");
+    if (!c->compiled) return fail(QS_E_PRECOND, "circuit is not compiled");
+    if (index < 0 || index >= (int)c->passes.size()) return fail(QS_E_ARG, "pass index out of range");
+    const Pass &p = c->passes[index];
+    int k, nt, nc;
+    if (p.gadget) {
+        bool xy = false;
+        nt = 0;
+        for (int code : p.paulis) {
+            if (code == 1 || code == 2) xy = true;
+            if (code != 0) nt++;
+        }
+        k = xy ? 0 : 1;
+        nc = 0;
+    } else {
+        nt = (int)p.sorted_targs.size();
+        nc = (int)p.ctrls.size();
+        const uint64_t groups = 1ULL << (c->num_qubits - nt - nc);
+        const bool mfma = p.kernel == kDenseMfma && c->precision == QS_C64 && nt >= 4 && groups >= 16;
+        k = mfma ? 3 : 2;
+    }
+    if (kernel) *kernel = k;
+    if (num_targs) *num_targs = nt;
+    if (num_ctrls) *num_ctrls = nc;
+    if (members) *members = p.members;
+    return QS_OK;
+}
+
+int qs_apply_circuit_passes(qs_qureg *q, qs_circuit *c, int first, int count)
+{
     if (!q || !c) return fail(QS_E_ARG, "null argument");
     if (q->is_density) return fail(QS_E_PRECOND, "circuits apply to statevectors");
     if (q->num_qubits != c->num_qubits) return fail(QS_E_ARG, "qubit counts differ");
     if (!c->compiled) return fail(QS_E_PRECOND, "circuit is not compiled");
     if (c->precision != q->precision) return fail(QS_E_TYPE, "circuit compiled for the other precision");
     if (c->dev && c->device != q->device) return fail(QS_E_PRECOND, "circuit matrices live on another device");
-    for (const auto &p : c->passes) {
+    if (first < 0 || count < 0 || first + count > (int)c->passes.size()) return fail(QS_E_ARG, "pass range out of bounds");
+    for (int pi = first; pi < first + count; pi++) {
+        const Pass &p = c->passes[pi];
         int rc;
         if (p.gadget) {
             rc = apply_raw_gadget(q, p.gtargs, p.paulis, p.theta);

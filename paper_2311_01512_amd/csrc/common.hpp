@@ -174,4 +174,8 @@ int mfma_preference();
 // Upper bound on the MFMA kernel's grid for a k-target gate.
 uint64_t mfma_block_cap(int k);
 
+// Key of a recorded circuit's contents (circuit.hip).
+uint64_t circuit_fingerprint(const qs_circuit *c);
+int circuit_num_qubits(const qs_circuit *c);
+
 }  // namespace qs

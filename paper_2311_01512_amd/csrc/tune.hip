@@ -1,9 +1,15 @@
-// Tuning knobs of the launch policy.  Defaults come from measurements on
-// MI355X; the environment can override them (QS_DENSE_KERNEL=vector|mfma,
-// QS_MFMA_BLOCKS=<max blocks of the MFMA kernel>).
+// Launch-policy knobs and the fusion-width autotuner.
+//
+// Knobs default to values measured on MI355X and can be overridden from the
+// environment: QS_DENSE_KERNEL=vector|mfma (dense gates of 4-6 targets on
+// complex64), QS_MFMA_BLOCKS=<max blocks of the MFMA kernel>.
 #include "common.hpp"
 
+#include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace qs {
 
@@ -30,4 +36,90 @@ uint64_t mfma_block_cap(int)
     return cap;
 }
 
+// (qubits, precision, circuit fingerprint) -> chosen fusion width
+using TuneKey = std::tuple<int, int, uint64_t>;
+static std::map<TuneKey, int> g_tuned;
+static std::mutex g_tune_mu;
+static bool g_file_loaded = false;
+
+static void load_cache_file()
+{
+    if (g_file_loaded) return;
+    g_file_loaded = true;
+    const char *path = std::getenv("QS_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    int n, p, k;
+    unsigned long long h;
+    while (std::fscanf(f, "fuse %d %d %llx %d\n", &n, &p, &h, &k) == 4) g_tuned[TuneKey(n, p, h)] = k;
+    std::fclose(f);
+}
+
+static void append_cache_file(const TuneKey &key, int k)
+{
+    const char *path = std::getenv("QS_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "fuse %d %d %llx %d\n", std::get<0>(key), std::get<1>(key),
+                 (unsigned long long)std::get<2>(key), k);
+    std::fclose(f);
+}
+
 }  // namespace qs
+
+using namespace qs;
+
+extern "C" int qs_circuit_autotune(qs_qureg *q, qs_circuit *c, const int *candidates, int num_candidates,
+                                   int *best_k, double *ms_out)
+{
+    if (!q || !c || !candidates || num_candidates < 1) return fail(QS_E_ARG, "bad autotune arguments");
+    if (q->num_qubits != circuit_num_qubits(c)) return fail(QS_E_ARG, "qubit counts differ");
+    const TuneKey key(q->num_qubits, q->precision, circuit_fingerprint(c));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_cache_file();
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end() && !ms_out) {
+            if (best_k) *best_k = it->second;
+            return qs_circuit_compile(c, it->second, q->precision);
+        }
+    }
+    hipEvent_t e0, e1;
+    QS_HIP(hipEventCreate(&e0));
+    QS_HIP(hipEventCreate(&e1));
+    int best = candidates[0];
+    float best_ms = 1e30f;
+    int rc = QS_OK;
+    for (int i = 0; i < num_candidates && rc == QS_OK; i++) {
+        rc = qs_circuit_compile(c, candidates[i], q->precision);
+        if (rc != QS_OK) break;
+        rc = qs_apply_circuit(q, c);   // untimed: first-touch and code loading
+        if (rc != QS_OK) break;
+        if (hipEventRecord(e0, q->stream) != hipSuccess) { rc = fail(QS_E_HIP, "hipEventRecord"); break; }
+        rc = qs_apply_circuit(q, c);
+        if (rc != QS_OK) break;
+        if (hipEventRecord(e1, q->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(QS_E_HIP, "event timing failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms_out) ms_out[i] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = candidates[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != QS_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[key] = best;
+        append_cache_file(key, best);
+    }
+    if (best_k) *best_k = best;
+    return qs_circuit_compile(c, best, q->precision);
+}

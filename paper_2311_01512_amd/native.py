@@ -70,6 +70,10 @@ _SIGS = {
     "qs_circuit_compile": [_P, _I, _I],
     "qs_circuit_stats": [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_uint64), C.POINTER(C.c_int)],
     "qs_apply_circuit": [_P, _P],
+    "qs_apply_circuit_passes": [_P, _P, _I, _I],
+    "qs_circuit_pass_info": [_P, _I, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                             C.POINTER(C.c_int)],
+    "qs_circuit_autotune": [_P, _P, _P, _I, C.POINTER(C.c_int), _PD],
 }
 
 for _name, _args in _SIGS.items():
@@ -281,3 +285,26 @@ def qs_circuit_stats(c):
 
 def qs_apply_circuit(q, c):
     check(lib.qs_apply_circuit(q, c), "qs_apply_circuit")
+
+
+def qs_apply_circuit_passes(q, c, first, count):
+    check(lib.qs_apply_circuit_passes(q, c, first, count), "qs_apply_circuit_passes")
+
+
+PASS_KERNELS = {0: "gadget_pairs", 1: "gadget_diag", 2: "dense_vector", 3: "dense_mfma"}
+
+
+def qs_circuit_pass_info(c, index):
+    k, nt, nc, m = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+    check(lib.qs_circuit_pass_info(c, index, C.byref(k), C.byref(nt), C.byref(nc), C.byref(m)),
+          "qs_circuit_pass_info")
+    return {"kernel": PASS_KERNELS[k.value], "num_targs": nt.value, "num_ctrls": nc.value, "members": m.value}
+
+
+def qs_circuit_autotune(q, c, candidates):
+    cand = ints(candidates)
+    best = C.c_int()
+    ms = np.zeros(cand.size, dtype=np.float64)
+    check(lib.qs_circuit_autotune(q, c, ptr(cand), cand.size, C.byref(best),
+                                  ms.ctypes.data_as(_PD)), "qs_circuit_autotune")
+    return best.value, ms
