@@ -256,6 +256,61 @@ int qs_circuit_pass_info(const qs_circuit *c, int index, int *kernel, int *num_t
 int qs_circuit_autotune(qs_qureg *q, qs_circuit *c, const int *candidates, int num_candidates, int *best_k,
                         double *ms_out);
 
+/* ---- batches: many parametrised circuits of uneven size, with energies and
+ *      adjoint gradients ------------------------------------------------------ */
+
+/*
+ * A batch holds many statevector circuits (1 <= N <= 30 qubits each) built
+ * from single-qubit rotations exp(i * scale * params[p] * P) (P = X, Y or Z,
+ * the Pauli gadget of Sec. "Pauli gadget" on one qubit), fixed single-qubit
+ * gates and CZ gates, each circuit with its own Pauli-sum observable H and
+ * parameter vector.  qs_batch_run starts every circuit from |0..0>, applies
+ * it, and returns E = <psi|H|psi> per circuit; with gradients it also runs
+ * the adjoint sweep: lambda = H psi, then for each operator from last to
+ * first, dE/dtheta_p += 2 Re(i scale <lambda|P|phi>) for a rotation, and
+ * phi, lambda <- U^dagger phi, U^dagger lambda.
+ *
+ * Execution: compile partitions every circuit into steps, each a set of at
+ * most T qubits (T = 12 for complex64, 11 for complex128; every qubit when
+ * N <= T) plus the operators that act inside it or are diagonal; a step
+ * gathers each 2^T-amplitude tile of the state into LDS, applies its
+ * operators there and writes the tile back.  Step s of every circuit runs
+ * in one kernel launch; the whole run is captured once into a HIP graph.
+ * Parameters are row-concatenated per circuit in creation order, as are the
+ * returned gradients.  The batch owns its device buffers; its stream is the
+ * one given to qs_batch_compile.  Calls on one batch must not overlap.
+ */
+typedef struct qs_batch qs_batch;
+int qs_batch_create(int precision, qs_batch **out);
+int qs_batch_destroy(qs_batch *b);
+/* Adds a circuit of num_qubits qubits with num_params parameters; *index
+ * receives its position. */
+int qs_batch_add_circuit(qs_batch *b, int num_qubits, int num_params, int *index);
+/* exp(i * scale * params[param] * P) on `qubit`, pauli 1 = X, 2 = Y, 3 = Z.
+ * RY(a) = exp(-i a Y / 2) is pauli 2 with scale -0.5. */
+int qs_batch_add_rotation(qs_batch *b, int circuit, int qubit, int pauli, int param, double scale);
+/* A fixed 2 x 2 gate (row-major (re, im) doubles) on `qubit`. */
+int qs_batch_add_gate1(qs_batch *b, int circuit, int qubit, const double *matrix);
+/* Controlled-Z on two distinct qubits (diagonal, symmetric). */
+int qs_batch_add_cz(qs_batch *b, int circuit, int q1, int q2);
+/* Observable of a circuit: num_terms Pauli strings of N codes each (term-
+ * major, qubit 0 first) with real coefficients. */
+int qs_batch_set_observable(qs_batch *b, int circuit, const int *paulis, const double *coeffs, int num_terms);
+/* Allocates the states (two per circuit), plans the steps, uploads the
+ * tables and captures the graphs on hip_stream (NULL = null stream).
+ * use_graph = 0 launches the kernels directly instead. */
+int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph);
+/* Runs the batch with the given parameters; energies receives one value per
+ * circuit; grads (NULL to skip the adjoint sweep) one per parameter. */
+int qs_batch_run(qs_batch *b, const double *params, double *energies, double *grads);
+/* Copies circuit `circuit`'s statevector (2^N (re, im) doubles) as left by
+ * the last run: the final state when that run skipped gradients. */
+int qs_batch_get_state(qs_batch *b, int circuit, double *re_im);
+/* Totals of the compiled batch; any pointer may be NULL.  logical_updates
+ * counts 2^N per operator of every circuit (one forward application). */
+int qs_batch_stats(const qs_batch *b, int *num_circuits, int *num_steps, uint64_t *total_amps,
+                   uint64_t *logical_updates);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,4 +16,7 @@ def __getattr__(name):
     if name == "Circuit":
         from .circuit import Circuit
         return Circuit
+    if name == "Batch":
+        from .batch import Batch
+        return Batch
     raise AttributeError(name)

@@ -1,0 +1,942 @@
+// Batched execution of many parametrised circuits of uneven size, with
+// per-circuit Pauli-sum energies and adjoint-method gradients.
+//
+// Each circuit is split into steps: a step owns a set Q of at most T qubits
+// (always including the lowest C qubits, so tiles are read in runs of 2^C
+// consecutive amplitudes) and the operators that act inside Q or are
+// diagonal.  A step streams the state through LDS one 2^|Q| tile at a time
+// (the tile number is spread over the qubits outside Q) and applies its
+// operators to the tile.  Operators are absorbed into a step only if they
+// commute with every operator left behind (no shared qubit), so the order of
+// the circuit is respected.  All circuits' s-th steps form one kernel launch.
+#include "common.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace qs {
+
+constexpr int kTileMax = 12;
+
+enum { BOP_ROT = 0, BOP_GATE = 1, BOP_CZ = 2 };
+
+struct BOp {
+    int kind, q0, q1, pauli, param;
+    double scale;
+    cd m[4];
+    uint64_t support() const { return (1ULL << q0) | (kind == BOP_CZ ? (1ULL << q1) : 0ULL); }
+};
+
+struct BStep {
+    uint64_t qmask;
+    std::vector<int> ops;
+};
+
+struct BCirc {
+    int n, num_params;
+    std::vector<BOp> ops;
+    std::vector<int> codes;
+    std::vector<double> coeffs;
+    std::vector<BStep> steps;
+    uint64_t amp_off;
+    int param_off;
+};
+
+// Device descriptors.
+struct DOp {
+    int kind;
+    int pos0, pos1;   // positions of q0 / q1 inside the step's qubit set, -1 if outside
+    int q0, q1;
+    int pauli;
+    int param;        // global parameter index (rotations)
+    int grad;         // rotation slot, -1 for other operators
+    uint64_t gpart;   // first gradient partial of this rotation (one per tile)
+    double scale;
+    double m[8];      // fixed gate, row-major (re, im)
+};
+
+struct DStep {
+    uint64_t amp_off;
+    InsertPlan plan;  // zeros at the step's qubits: spreads the tile number
+    int qn;
+    int qpos[kTileMax];
+    int op_begin, op_end;
+};
+
+struct DTerm {
+    uint64_t x, yz;
+    double cre, cim;  // h_n i^{#Y}
+};
+
+__device__ __forceinline__ double bwave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// (re, im) summed over the block; valid in thread 0.
+__device__ void bblock_sum2(double &re, double &im, double *scratch)
+{
+    re = bwave_sum(re);
+    im = bwave_sum(im);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        scratch[2 * wave] = re;
+        scratch[2 * wave + 1] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
+            a += scratch[2 * w];
+            b += scratch[2 * w + 1];
+        }
+        re = a;
+        im = b;
+    }
+}
+
+__device__ __forceinline__ uint64_t tile_offset(int j, const DStep &st)
+{
+    uint64_t o = 0;
+    for (int b = 0; b < st.qn; b++) o |= (uint64_t)((j >> b) & 1) << st.qpos[b];
+    return o;
+}
+
+// 2 x 2 matrix of an operator; dir = -1 gives its adjoint.
+template <typename R>
+__device__ void op_matrix(const DOp &op, const double *params, int dir, C2<R> u[4])
+{
+    if (op.kind == BOP_ROT) {
+        const double ang = dir * op.scale * params[op.param];
+        double s, c;
+        sincos(ang, &s, &c);
+        if (op.pauli == 1) {          // c 1 + i s X
+            u[0] = mk<R>(c, 0); u[1] = mk<R>(0, s); u[2] = mk<R>(0, s); u[3] = mk<R>(c, 0);
+        } else if (op.pauli == 2) {   // c 1 + i s Y
+            u[0] = mk<R>(c, 0); u[1] = mk<R>(s, 0); u[2] = mk<R>(-s, 0); u[3] = mk<R>(c, 0);
+        } else {                      // c 1 + i s Z
+            u[0] = mk<R>(c, s); u[1] = mk<R>(0, 0); u[2] = mk<R>(0, 0); u[3] = mk<R>(c, -s);
+        }
+    } else if (dir > 0) {
+        for (int k = 0; k < 4; k++) u[k] = mk<R>((R)op.m[2 * k], (R)op.m[2 * k + 1]);
+    } else {                          // conjugate transpose
+        u[0] = mk<R>((R)op.m[0], (R)-op.m[1]);
+        u[1] = mk<R>((R)op.m[4], (R)-op.m[5]);
+        u[2] = mk<R>((R)op.m[2], (R)-op.m[3]);
+        u[3] = mk<R>((R)op.m[6], (R)-op.m[7]);
+    }
+}
+
+template <typename R>
+__device__ void tile_gate(C2<R> *v, int qn, int pos, const C2<R> u[4])
+{
+    const int np = 1 << (qn - 1);
+    const int lo = (1 << pos) - 1;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        const int j0 = (p & lo) | ((p & ~lo) << 1), j1 = j0 | (1 << pos);
+        const C2<R> a = v[j0], b = v[j1];
+        C2<R> x = mk<R>(0, 0), y = mk<R>(0, 0);
+        cmac<R>(x, u[0], a);
+        cmac<R>(x, u[1], b);
+        cmac<R>(y, u[2], a);
+        cmac<R>(y, u[3], b);
+        v[j0] = x;
+        v[j1] = y;
+    }
+}
+
+template <typename R>
+__device__ void tile_cz(C2<R> *v, int qn, const DOp &op, uint64_t base)
+{
+    const int T = 1 << qn;
+    const int b0 = op.pos0 < 0 ? (int)((base >> op.q0) & 1) : -1;
+    const int b1 = op.pos1 < 0 ? (int)((base >> op.q1) & 1) : -1;
+    if (b0 == 0 || b1 == 0) return;   // the tile lies where a control bit is 0
+    for (int j = threadIdx.x; j < T; j += blockDim.x) {
+        const int x0 = b0 < 0 ? (j >> op.pos0) & 1 : 1;
+        const int x1 = b1 < 0 ? (j >> op.pos1) & 1 : 1;
+        if (x0 & x1) v[j] = mk<R>(-v[j].x, -v[j].y);
+    }
+}
+
+template <typename R>
+__device__ void tile_apply(C2<R> *v, int qn, const DOp &op, uint64_t base, const double *params, int dir)
+{
+    if (op.kind == BOP_CZ) {
+        tile_cz<R>(v, qn, op, base);
+    } else {
+        C2<R> u[4];
+        op_matrix<R>(op, params, dir, u);
+        tile_gate<R>(v, qn, op.pos0, u);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_forward(C2<R> *__restrict__ amps, const DStep *__restrict__ steps,
+                                                        const DOp *__restrict__ ops, const uint2 *__restrict__ work,
+                                                        const double *__restrict__ params)
+{
+    extern __shared__ unsigned char lds_raw[];
+    C2<R> *v = reinterpret_cast<C2<R> *>(lds_raw);
+    const uint2 w = work[blockIdx.x];
+    const DStep &st = steps[w.x];
+    const uint64_t base = insert_zeros(w.y, st.plan);
+    C2<R> *a = amps + st.amp_off;
+    const int T = 1 << st.qn;
+    for (int j = threadIdx.x; j < T; j += blockDim.x) v[j] = a[base | tile_offset(j, st)];
+    __syncthreads();
+    for (int k = st.op_begin; k < st.op_end; k++) {
+        tile_apply<R>(v, st.qn, ops[k], base, params, +1);
+        __syncthreads();
+    }
+    for (int j = threadIdx.x; j < T; j += blockDim.x) a[base | tile_offset(j, st)] = v[j];
+}
+
+// Adjoint sweep over one tile of phi and lambda: for each operator, last
+// first, the rotation's partial <lambda|P|phi> over the tile, then
+// phi <- U^dagger phi and lambda <- U^dagger lambda.
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_backward(C2<R> *__restrict__ amps, uint64_t lambda_base,
+                                                         const DStep *__restrict__ steps, const DOp *__restrict__ ops,
+                                                         const uint2 *__restrict__ work,
+                                                         const double *__restrict__ params, double *__restrict__ gpart)
+{
+    extern __shared__ unsigned char lds_raw[];
+    __shared__ double red[32];
+    const uint2 w = work[blockIdx.x];
+    const DStep &st = steps[w.x];
+    const int T = 1 << st.qn;
+    C2<R> *phi = reinterpret_cast<C2<R> *>(lds_raw);
+    C2<R> *lam = phi + T;
+    const uint64_t base = insert_zeros(w.y, st.plan);
+    C2<R> *a = amps + st.amp_off;
+    C2<R> *l = amps + lambda_base + st.amp_off;
+    for (int j = threadIdx.x; j < T; j += blockDim.x) {
+        const uint64_t o = base | tile_offset(j, st);
+        phi[j] = a[o];
+        lam[j] = l[o];
+    }
+    __syncthreads();
+    for (int k = st.op_end - 1; k >= st.op_begin; k--) {
+        const DOp &op = ops[k];
+        if (op.grad >= 0) {
+            double re = 0.0, im = 0.0;
+            const int pos = op.pos0;
+            for (int j = threadIdx.x; j < T; j += blockDim.x) {
+                const int bit = (j >> pos) & 1;
+                C2<R> p;   // (P phi)_j
+                if (op.pauli == 1) {
+                    p = phi[j ^ (1 << pos)];
+                } else if (op.pauli == 2) {
+                    const C2<R> x = phi[j ^ (1 << pos)];     // -i x if bit = 0, +i x if bit = 1
+                    p = bit ? mk<R>(-x.y, x.x) : mk<R>(x.y, -x.x);
+                } else {
+                    p = bit ? mk<R>(-phi[j].x, -phi[j].y) : phi[j];
+                }
+                const C2<R> y = lam[j];
+                re += (double)y.x * p.x + (double)y.y * p.y;
+                im += (double)y.x * p.y - (double)y.y * p.x;
+            }
+            bblock_sum2(re, im, red);
+            if (threadIdx.x == 0) {
+                gpart[2 * (op.gpart + w.y)] = re;
+                gpart[2 * (op.gpart + w.y) + 1] = im;
+            }
+            __syncthreads();
+        }
+        if (op.kind == BOP_CZ) {
+            tile_cz<R>(phi, st.qn, op, base);
+            tile_cz<R>(lam, st.qn, op, base);
+        } else {
+            C2<R> u[4];
+            op_matrix<R>(op, params, -1, u);
+            tile_gate<R>(phi, st.qn, op.pos0, u);
+            tile_gate<R>(lam, st.qn, op.pos0, u);
+        }
+        __syncthreads();
+    }
+    for (int j = threadIdx.x; j < T; j += blockDim.x) {
+        const uint64_t o = base | tile_offset(j, st);
+        a[o] = phi[j];
+        l[o] = lam[j];
+    }
+}
+
+// Per-block circuit table of the flat amplitude range.
+struct BlockMap {
+    const int *circ;         // circuit of each 256-amplitude block
+    const uint64_t *start;   // first local index of each block
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_init(C2<R> *__restrict__ amps, BlockMap bm,
+                                                     const uint64_t *__restrict__ offs, const int *__restrict__ nq)
+{
+    const int c = bm.circ[blockIdx.x];
+    const uint64_t i = bm.start[blockIdx.x] + threadIdx.x;
+    if (i < (1ULL << nq[c])) amps[offs[c] + i] = mk<R>(i == 0 ? R(1) : R(0), R(0));
+}
+
+// lambda = H phi with (P phi)_i = beta_{i^x} phi_{i^x}, beta_y = i^{#Y} (-1)^{popc(y & yz)};
+// energy partial sum_i conj(phi_i) lambda_i per block.
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_hamiltonian(C2<R> *__restrict__ amps, uint64_t lambda_base, BlockMap bm,
+                                                            const uint64_t *__restrict__ offs,
+                                                            const int *__restrict__ nq, const int *__restrict__ term_off,
+                                                            const DTerm *__restrict__ terms, double *__restrict__ epart)
+{
+    __shared__ double red[32];
+    const int c = bm.circ[blockIdx.x];
+    const uint64_t i = bm.start[blockIdx.x] + threadIdx.x;
+    double re = 0.0, im = 0.0;
+    if (i < (1ULL << nq[c])) {
+        const C2<R> *phi = amps + offs[c];
+        double lr = 0.0, li = 0.0;
+        for (int t = term_off[c]; t < term_off[c + 1]; t++) {
+            const DTerm tm = terms[t];
+            const uint64_t j = i ^ tm.x;
+            const double s = (__popcll(j & tm.yz) & 1) ? -1.0 : 1.0;
+            const C2<R> x = phi[j];
+            lr += s * (tm.cre * x.x - tm.cim * x.y);
+            li += s * (tm.cre * x.y + tm.cim * x.x);
+        }
+        amps[lambda_base + offs[c] + i] = mk<R>((R)lr, (R)li);
+        const C2<R> p = phi[i];
+        re = (double)p.x * lr + (double)p.y * li;
+        im = (double)p.x * li - (double)p.y * lr;
+    }
+    bblock_sum2(re, im, red);
+    if (threadIdx.x == 0) {
+        epart[2 * blockIdx.x] = re;
+        epart[2 * blockIdx.x + 1] = im;
+    }
+}
+
+// One block per circuit: fixed-order sum of its blocks' energy partials.
+__global__ __launch_bounds__(256) void k_batch_energy(const double *__restrict__ epart, const int *__restrict__ first_block,
+                                                       double *__restrict__ energy)
+{
+    __shared__ double red[32];
+    const int c = blockIdx.x;
+    double re = 0.0, im = 0.0;
+    for (int b = first_block[c] + threadIdx.x; b < first_block[c + 1]; b += blockDim.x) {
+        re += epart[2 * b];
+        im += epart[2 * b + 1];
+    }
+    bblock_sum2(re, im, red);
+    if (threadIdx.x == 0) {
+        energy[2 * c] = re;
+        energy[2 * c + 1] = im;
+    }
+}
+
+// One thread per rotation: fixed-order sum over its tiles.
+__global__ __launch_bounds__(256) void k_batch_grad(const double *__restrict__ gpart, const uint64_t *__restrict__ first,
+                                                     int num_rot, double *__restrict__ out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= num_rot) return;
+    double re = 0.0, im = 0.0;
+    for (uint64_t t = first[r]; t < first[r + 1]; t++) {
+        re += gpart[2 * t];
+        im += gpart[2 * t + 1];
+    }
+    out[2 * r] = re;
+    out[2 * r + 1] = im;
+}
+
+}  // namespace qs
+
+using namespace qs;
+
+struct qs_batch {
+    int precision;
+    std::vector<BCirc> circs;
+    bool compiled = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int use_graph = 1;
+    int tile_qubits = 12, low_qubits = 3;
+    // device
+    void *amps = nullptr;
+    uint64_t total_amps = 0;     // per region (phi); lambda follows
+    DStep *d_steps = nullptr;
+    DOp *d_ops = nullptr;
+    std::vector<uint2 *> d_work;          // per phase
+    std::vector<unsigned> phase_blocks;
+    int *d_bm_circ = nullptr;
+    uint64_t *d_bm_start = nullptr;
+    unsigned amp_blocks = 0;
+    uint64_t *d_offs = nullptr;
+    int *d_nq = nullptr;
+    int *d_term_off = nullptr;
+    DTerm *d_terms = nullptr;
+    int *d_first_block = nullptr;
+    double *d_epart = nullptr, *d_energy = nullptr, *h_energy = nullptr;
+    double *d_gpart = nullptr, *d_gop = nullptr, *h_gop = nullptr;
+    uint64_t *d_gfirst = nullptr;
+    int num_rot = 0;
+    std::vector<int> rot_param;      // global parameter of each rotation slot
+    std::vector<double> rot_scale;
+    double *d_params = nullptr, *h_params = nullptr;
+    int total_params = 0;
+    hipGraphExec_t g_fwd = nullptr, g_full = nullptr;
+    hipGraph_t gr_fwd = nullptr, gr_full = nullptr;
+    bool last_run_had_grads = false;
+};
+
+namespace qs {
+
+static void plan_circuit(BCirc &c, int TQ, int C)
+{
+    const int L = (int)c.ops.size();
+    std::vector<char> placed(L, 0);
+    int remaining = L;
+    const uint64_t all = (c.n >= 64) ? ~0ULL : ((1ULL << c.n) - 1ULL);
+    c.steps.clear();
+    while (remaining > 0) {
+        uint64_t Q = 0;
+        if (c.n <= TQ) {
+            Q = all;
+        } else {
+            for (int b = 0; b < C; b++) Q |= 1ULL << b;
+            uint64_t blocked = 0;
+            for (int k = 0; k < L && __builtin_popcountll(Q) < TQ; k++) {
+                if (placed[k]) continue;
+                const uint64_t s = c.ops[k].support();
+                if (s & blocked) {
+                    blocked |= s;
+                    continue;
+                }
+                if (c.ops[k].kind == BOP_CZ) continue;   // diagonal: needs no tile qubit
+                Q |= s;
+            }
+        }
+        BStep st;
+        st.qmask = Q;
+        uint64_t blocked = 0;
+        for (int k = 0; k < L; k++) {
+            if (placed[k]) continue;
+            const BOp &op = c.ops[k];
+            const uint64_t s = op.support();
+            if (s & blocked) {
+                blocked |= s;
+                continue;
+            }
+            if (op.kind == BOP_CZ || (s & ~Q) == 0) {
+                st.ops.push_back(k);
+                placed[k] = 1;
+                remaining--;
+            } else {
+                blocked |= s;
+            }
+        }
+        c.steps.push_back(std::move(st));
+    }
+}
+
+static int launch_phase_kernels(qs_batch *b, bool grads)
+{
+    const size_t ab = b->precision == QS_C64 ? 8 : 16;
+    const size_t lds1 = ((size_t)1 << b->tile_qubits) * ab;
+    const int P = (int)b->d_work.size();
+    // initial states
+    if (b->precision == QS_C64)
+        hipLaunchKernelGGL(k_batch_init<float>, dim3(b->amp_blocks), dim3(256), 0, b->stream, (float2 *)b->amps,
+                           BlockMap{b->d_bm_circ, b->d_bm_start}, (const uint64_t *)b->d_offs, (const int *)b->d_nq);
+    else
+        hipLaunchKernelGGL(k_batch_init<double>, dim3(b->amp_blocks), dim3(256), 0, b->stream, (double2 *)b->amps,
+                           BlockMap{b->d_bm_circ, b->d_bm_start}, (const uint64_t *)b->d_offs, (const int *)b->d_nq);
+    QS_LAUNCH_CHECK();
+    for (int p = 0; p < P; p++) {
+        if (b->phase_blocks[p] == 0) continue;
+        if (b->precision == QS_C64)
+            hipLaunchKernelGGL(k_batch_forward<float>, dim3(b->phase_blocks[p]), dim3(256), lds1, b->stream,
+                               (float2 *)b->amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
+                               (const uint2 *)b->d_work[p], (const double *)b->d_params);
+        else
+            hipLaunchKernelGGL(k_batch_forward<double>, dim3(b->phase_blocks[p]), dim3(256), lds1, b->stream,
+                               (double2 *)b->amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
+                               (const uint2 *)b->d_work[p], (const double *)b->d_params);
+        QS_LAUNCH_CHECK();
+    }
+    const BlockMap bm{b->d_bm_circ, b->d_bm_start};
+    if (b->precision == QS_C64)
+        hipLaunchKernelGGL(k_batch_hamiltonian<float>, dim3(b->amp_blocks), dim3(256), 0, b->stream, (float2 *)b->amps,
+                           b->total_amps, bm, (const uint64_t *)b->d_offs, (const int *)b->d_nq,
+                           (const int *)b->d_term_off, (const DTerm *)b->d_terms, b->d_epart);
+    else
+        hipLaunchKernelGGL(k_batch_hamiltonian<double>, dim3(b->amp_blocks), dim3(256), 0, b->stream,
+                           (double2 *)b->amps, b->total_amps, bm, (const uint64_t *)b->d_offs, (const int *)b->d_nq,
+                           (const int *)b->d_term_off, (const DTerm *)b->d_terms, b->d_epart);
+    QS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_batch_energy, dim3((unsigned)b->circs.size()), dim3(256), 0, b->stream,
+                       (const double *)b->d_epart, (const int *)b->d_first_block, b->d_energy);
+    QS_LAUNCH_CHECK();
+    if (!grads) return QS_OK;
+    for (int p = P - 1; p >= 0; p--) {
+        if (b->phase_blocks[p] == 0) continue;
+        if (b->precision == QS_C64)
+            hipLaunchKernelGGL(k_batch_backward<float>, dim3(b->phase_blocks[p]), dim3(256), 2 * lds1, b->stream,
+                               (float2 *)b->amps, b->total_amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
+                               (const uint2 *)b->d_work[p], (const double *)b->d_params, b->d_gpart);
+        else
+            hipLaunchKernelGGL(k_batch_backward<double>, dim3(b->phase_blocks[p]), dim3(256), 2 * lds1, b->stream,
+                               (double2 *)b->amps, b->total_amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
+                               (const uint2 *)b->d_work[p], (const double *)b->d_params, b->d_gpart);
+        QS_LAUNCH_CHECK();
+    }
+    if (b->num_rot > 0) {
+        hipLaunchKernelGGL(k_batch_grad, dim3((b->num_rot + 255) / 256), dim3(256), 0, b->stream,
+                           (const double *)b->d_gpart, (const uint64_t *)b->d_gfirst, b->num_rot, b->d_gop);
+        QS_LAUNCH_CHECK();
+    }
+    return QS_OK;
+}
+
+static int capture(qs_batch *b, bool grads, hipGraph_t *g, hipGraphExec_t *ge)
+{
+    QS_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = launch_phase_kernels(b, grads);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (rc != QS_OK) return rc;
+    if (e != hipSuccess) return fail(QS_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    QS_HIP(hipGraphInstantiate(ge, graph, nullptr, nullptr, 0));
+    *g = graph;
+    return QS_OK;
+}
+
+template <typename P>
+static int upload(P **dst, const void *src, size_t bytes)
+{
+    if (hipMalloc((void **)dst, bytes > 0 ? bytes : 16) != hipSuccess) {
+        (void)hipGetLastError();
+        *dst = nullptr;
+        return fail(QS_E_ALLOC, "device allocation failed");
+    }
+    if (src && bytes > 0) QS_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    return QS_OK;
+}
+
+static void release(qs_batch *b)
+{
+    auto f = [](void *p) {
+        if (p) (void)hipFree(p);
+    };
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    b->own_stream = false;
+    b->stream = nullptr;
+    if (b->g_fwd) (void)hipGraphExecDestroy(b->g_fwd);
+    if (b->g_full) (void)hipGraphExecDestroy(b->g_full);
+    if (b->gr_fwd) (void)hipGraphDestroy(b->gr_fwd);
+    if (b->gr_full) (void)hipGraphDestroy(b->gr_full);
+    b->g_fwd = b->g_full = nullptr;
+    b->gr_fwd = b->gr_full = nullptr;
+    f(b->amps);
+    f(b->d_steps);
+    f(b->d_ops);
+    for (auto *w : b->d_work) f(w);
+    b->d_work.clear();
+    f(b->d_bm_circ);
+    f(b->d_bm_start);
+    f(b->d_offs);
+    f(b->d_nq);
+    f(b->d_term_off);
+    f(b->d_terms);
+    f(b->d_first_block);
+    f(b->d_epart);
+    f(b->d_energy);
+    f(b->d_gpart);
+    f(b->d_gop);
+    f(b->d_gfirst);
+    f(b->d_params);
+    if (b->h_energy) (void)hipHostFree(b->h_energy);
+    if (b->h_gop) (void)hipHostFree(b->h_gop);
+    if (b->h_params) (void)hipHostFree(b->h_params);
+    b->amps = nullptr;
+    b->d_steps = nullptr;
+    b->d_ops = nullptr;
+    b->d_bm_circ = nullptr;
+    b->d_bm_start = nullptr;
+    b->d_offs = nullptr;
+    b->d_nq = nullptr;
+    b->d_term_off = nullptr;
+    b->d_terms = nullptr;
+    b->d_first_block = nullptr;
+    b->d_epart = b->d_energy = b->h_energy = nullptr;
+    b->d_gpart = b->d_gop = b->h_gop = nullptr;
+    b->d_gfirst = nullptr;
+    b->d_params = b->h_params = nullptr;
+    b->compiled = false;
+}
+
+}  // namespace qs
+
+extern "C" {
+
+int qs_batch_create(int precision, qs_batch **out)
+{
+    if (!out) return fail(QS_E_ARG, "null output pointer");
+    if (precision != QS_C64 && precision != QS_C128) return fail(QS_E_ARG, "bad precision");
+    qs_batch *b = new (std::nothrow) qs_batch{};
+    if (!b) return fail(QS_E_ALLOC, "host allocation failed");
+    b->precision = precision;
+    b->tile_qubits = precision == QS_C64 ? 12 : 11;
+    b->low_qubits = precision == QS_C64 ? 3 : 2;
+    *out = b;
+    return QS_OK;
+}
+
+int qs_batch_destroy(qs_batch *b)
+{
+    if (!b) return QS_OK;
+    if (b->compiled) (void)hipStreamSynchronize(b->stream);
+    release(b);
+    delete b;
+    return QS_OK;
+}
+
+int qs_batch_add_circuit(qs_batch *b, int num_qubits, int num_params, int *index)
+{
+    if (!b) return fail(QS_E_ARG, "null batch");
+    if (num_qubits < 1 || num_qubits > 30) return fail(QS_E_ARG, "batch circuits have 1 to 30 qubits");
+    if (num_params < 0) return fail(QS_E_ARG, "negative parameter count");
+    BCirc c{};
+    c.n = num_qubits;
+    c.num_params = num_params;
+    b->circs.push_back(std::move(c));
+    b->compiled = false;
+    if (index) *index = (int)b->circs.size() - 1;
+    return QS_OK;
+}
+
+static BCirc *circ_at(qs_batch *b, int i)
+{
+    if (!b || i < 0 || i >= (int)b->circs.size()) return nullptr;
+    return &b->circs[i];
+}
+
+int qs_batch_add_rotation(qs_batch *b, int circuit, int qubit, int pauli, int param, double scale)
+{
+    BCirc *c = circ_at(b, circuit);
+    if (!c) return fail(QS_E_ARG, "no such circuit");
+    if (qubit < 0 || qubit >= c->n) return fail(QS_E_ARG, "qubit out of range");
+    if (pauli < 1 || pauli > 3) return fail(QS_E_ARG, "rotation Pauli is 1 (X), 2 (Y) or 3 (Z)");
+    if (param < 0 || param >= c->num_params) return fail(QS_E_ARG, "parameter index out of range");
+    BOp op{};
+    op.kind = BOP_ROT;
+    op.q0 = qubit;
+    op.q1 = qubit;
+    op.pauli = pauli;
+    op.param = param;
+    op.scale = scale;
+    c->ops.push_back(op);
+    b->compiled = false;
+    return QS_OK;
+}
+
+int qs_batch_add_gate1(qs_batch *b, int circuit, int qubit, const double *m)
+{
+    BCirc *c = circ_at(b, circuit);
+    if (!c) return fail(QS_E_ARG, "no such circuit");
+    if (!m) return fail(QS_E_ARG, "null matrix");
+    if (qubit < 0 || qubit >= c->n) return fail(QS_E_ARG, "qubit out of range");
+    BOp op{};
+    op.kind = BOP_GATE;
+    op.q0 = qubit;
+    op.q1 = qubit;
+    for (int k = 0; k < 4; k++) op.m[k] = cd(m[2 * k], m[2 * k + 1]);
+    c->ops.push_back(op);
+    b->compiled = false;
+    return QS_OK;
+}
+
+int qs_batch_add_cz(qs_batch *b, int circuit, int q1, int q2)
+{
+    BCirc *c = circ_at(b, circuit);
+    if (!c) return fail(QS_E_ARG, "no such circuit");
+    if (q1 < 0 || q1 >= c->n || q2 < 0 || q2 >= c->n || q1 == q2) return fail(QS_E_ARG, "bad CZ qubits");
+    BOp op{};
+    op.kind = BOP_CZ;
+    op.q0 = q1;
+    op.q1 = q2;
+    c->ops.push_back(op);
+    b->compiled = false;
+    return QS_OK;
+}
+
+int qs_batch_set_observable(qs_batch *b, int circuit, const int *paulis, const double *coeffs, int num_terms)
+{
+    BCirc *c = circ_at(b, circuit);
+    if (!c) return fail(QS_E_ARG, "no such circuit");
+    if (num_terms < 0 || (num_terms > 0 && (!paulis || !coeffs))) return fail(QS_E_ARG, "bad observable");
+    for (int i = 0; i < num_terms * c->n; i++)
+        if (paulis[i] < 0 || paulis[i] > 3) return fail(QS_E_ARG, "Pauli codes are 0..3");
+    c->codes.assign(paulis, paulis + (size_t)num_terms * c->n);
+    c->coeffs.assign(coeffs, coeffs + num_terms);
+    b->compiled = false;
+    return QS_OK;
+}
+
+int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
+{
+    if (!b) return fail(QS_E_ARG, "null batch");
+    if (b->circs.empty()) return fail(QS_E_ARG, "empty batch");
+    if (b->compiled) (void)hipStreamSynchronize(b->stream);
+    release(b);
+    b->use_graph = use_graph ? 1 : 0;
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        // the legacy null stream cannot be captured: use a stream of our own
+        // (default priority)
+        QS_HIP(hipStreamCreate(&b->stream));
+        b->own_stream = true;
+    }
+    const size_t ab = b->precision == QS_C64 ? 8 : 16;
+    {
+        // the adjoint sweep holds two tiles in LDS
+        int dev = 0, max_lds = 0;
+        QS_HIP(hipGetDevice(&dev));
+        QS_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        b->tile_qubits = b->precision == QS_C64 ? 12 : 11;
+        while (b->tile_qubits > b->low_qubits + 1 && (2 * ((size_t)1 << b->tile_qubits) * ab + 512) > (size_t)max_lds)
+            b->tile_qubits--;
+    }
+    const int TQ = b->tile_qubits, C = b->low_qubits;
+
+    // layout: each circuit's amplitudes start on a 256-amplitude boundary
+    uint64_t off = 0;
+    int poff = 0;
+    size_t max_steps = 0;
+    for (auto &c : b->circs) {
+        plan_circuit(c, TQ, C);
+        c.amp_off = off;
+        off += ((1ULL << c.n) + 255) & ~255ULL;
+        c.param_off = poff;
+        poff += c.num_params;
+        max_steps = std::max(max_steps, c.steps.size());
+    }
+    b->total_amps = off;
+    b->total_params = poff;
+
+    // steps, operators, rotation slots and gradient partials
+    std::vector<DStep> steps;
+    std::vector<DOp> ops;
+    std::vector<uint64_t> gfirst{0};
+    b->rot_param.clear();
+    b->rot_scale.clear();
+    std::vector<std::vector<int>> step_index(b->circs.size());
+    for (size_t ci = 0; ci < b->circs.size(); ci++) {
+        BCirc &c = b->circs[ci];
+        for (auto &s : c.steps) {
+            DStep d{};
+            d.amp_off = c.amp_off;
+            std::vector<int> qs_;
+            for (int q = 0; q < c.n; q++)
+                if ((s.qmask >> q) & 1) qs_.push_back(q);
+            d.plan = make_insert_plan(qs_);
+            d.qn = (int)qs_.size();
+            for (int k = 0; k < d.qn; k++) d.qpos[k] = qs_[k];
+            d.op_begin = (int)ops.size();
+            const uint64_t tiles = 1ULL << (c.n - d.qn);
+            for (int k : s.ops) {
+                const BOp &o = c.ops[k];
+                DOp x{};
+                x.kind = o.kind;
+                x.q0 = o.q0;
+                x.q1 = o.q1;
+                auto pos = [&](int q) {
+                    auto it = std::find(qs_.begin(), qs_.end(), q);
+                    return it == qs_.end() ? -1 : (int)(it - qs_.begin());
+                };
+                x.pos0 = pos(o.q0);
+                x.pos1 = pos(o.q1);
+                x.pauli = o.pauli;
+                x.param = c.param_off + o.param;
+                x.scale = o.scale;
+                for (int m = 0; m < 4; m++) {
+                    x.m[2 * m] = o.m[m].real();
+                    x.m[2 * m + 1] = o.m[m].imag();
+                }
+                x.grad = -1;
+                if (o.kind == BOP_ROT) {
+                    x.grad = (int)b->rot_param.size();
+                    x.gpart = gfirst.back();
+                    gfirst.push_back(gfirst.back() + tiles);
+                    b->rot_param.push_back(c.param_off + o.param);
+                    b->rot_scale.push_back(o.scale);
+                }
+                ops.push_back(x);
+            }
+            d.op_end = (int)ops.size();
+            step_index[ci].push_back((int)steps.size());
+            steps.push_back(d);
+        }
+    }
+    b->num_rot = (int)b->rot_param.size();
+
+    // per-phase work lists: (step, tile) per block
+    std::vector<std::vector<uint2>> work(max_steps);
+    for (size_t ci = 0; ci < b->circs.size(); ci++) {
+        const BCirc &c = b->circs[ci];
+        for (size_t s = 0; s < c.steps.size(); s++) {
+            const int si = step_index[ci][s];
+            const uint64_t tiles = 1ULL << (c.n - steps[si].qn);
+            for (uint64_t t = 0; t < tiles; t++) work[s].push_back(make_uint2((unsigned)si, (unsigned)t));
+        }
+    }
+
+    // 256-amplitude block map, observables
+    std::vector<int> bm_circ, first_block, nq, term_off{0};
+    std::vector<uint64_t> bm_start, offs;
+    std::vector<DTerm> terms;
+    const cd eta[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+    for (size_t ci = 0; ci < b->circs.size(); ci++) {
+        const BCirc &c = b->circs[ci];
+        first_block.push_back((int)bm_circ.size());
+        for (uint64_t s = 0; s < (1ULL << c.n); s += 256) {
+            bm_circ.push_back((int)ci);
+            bm_start.push_back(s);
+        }
+        offs.push_back(c.amp_off);
+        nq.push_back(c.n);
+        const int T = (int)c.coeffs.size();
+        for (int t = 0; t < T; t++) {
+            DTerm d{};
+            int ny = 0;
+            for (int q = 0; q < c.n; q++) {
+                const int code = c.codes[(size_t)t * c.n + q];
+                if (code == 1 || code == 2) d.x |= 1ULL << q;
+                if (code == 2 || code == 3) d.yz |= 1ULL << q;
+                if (code == 2) ny++;
+            }
+            const cd cf = c.coeffs[t] * eta[ny & 3];
+            d.cre = cf.real();
+            d.cim = cf.imag();
+            terms.push_back(d);
+        }
+        term_off.push_back((int)terms.size());
+    }
+    first_block.push_back((int)bm_circ.size());
+    b->amp_blocks = (unsigned)bm_circ.size();
+
+    int rc = QS_OK;
+    auto up = [&](auto **dst, const auto &vec) {
+        if (rc == QS_OK) rc = upload(dst, vec.data(), vec.size() * sizeof(vec[0]));
+    };
+    if (hipMalloc(&b->amps, 2 * b->total_amps * ab) != hipSuccess) {
+        (void)hipGetLastError();
+        b->amps = nullptr;
+        return fail(QS_E_ALLOC, "device allocation of the batch states failed");
+    }
+    up(&b->d_steps, steps);
+    up(&b->d_ops, ops);
+    up(&b->d_bm_circ, bm_circ);
+    up(&b->d_bm_start, bm_start);
+    up(&b->d_offs, offs);
+    up(&b->d_nq, nq);
+    up(&b->d_term_off, term_off);
+    up(&b->d_terms, terms);
+    up(&b->d_first_block, first_block);
+    up(&b->d_gfirst, gfirst);
+    if (rc != QS_OK) return rc;
+    for (auto &w : work) {
+        uint2 *d = nullptr;
+        rc = upload(&d, w.data(), w.size() * sizeof(uint2));
+        if (rc != QS_OK) return rc;
+        b->d_work.push_back(d);
+        b->phase_blocks.push_back((unsigned)w.size());
+    }
+    if ((rc = upload(&b->d_epart, nullptr, sizeof(double) * 2 * bm_circ.size())) != QS_OK) return rc;
+    if ((rc = upload(&b->d_energy, nullptr, sizeof(double) * 2 * b->circs.size())) != QS_OK) return rc;
+    if ((rc = upload(&b->d_gpart, nullptr, sizeof(double) * 2 * gfirst.back())) != QS_OK) return rc;
+    if ((rc = upload(&b->d_gop, nullptr, sizeof(double) * 2 * std::max(1, b->num_rot))) != QS_OK) return rc;
+    if ((rc = upload(&b->d_params, nullptr, sizeof(double) * std::max(1, b->total_params))) != QS_OK) return rc;
+    if (hipHostMalloc(&b->h_energy, sizeof(double) * 2 * b->circs.size(), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&b->h_gop, sizeof(double) * 2 * std::max(1, b->num_rot), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&b->h_params, sizeof(double) * std::max(1, b->total_params), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(QS_E_ALLOC, "pinned host allocation failed");
+    }
+    if (b->use_graph) {
+        if ((rc = capture(b, false, &b->gr_fwd, &b->g_fwd)) != QS_OK) return rc;
+        if ((rc = capture(b, true, &b->gr_full, &b->g_full)) != QS_OK) return rc;
+    }
+    b->compiled = true;
+    return QS_OK;
+}
+
+int qs_batch_run(qs_batch *b, const double *params, double *energies, double *grads)
+{
+    if (!b) return fail(QS_E_ARG, "null batch");
+    if (!b->compiled) return fail(QS_E_PRECOND, "batch is not compiled");
+    if (b->total_params > 0 && !params) return fail(QS_E_ARG, "null parameters");
+    const bool want_grads = grads != nullptr;
+    QS_HIP(hipStreamSynchronize(b->stream));
+    if (b->total_params > 0) {
+        std::memcpy(b->h_params, params, sizeof(double) * b->total_params);
+        QS_HIP(hipMemcpyAsync(b->d_params, b->h_params, sizeof(double) * b->total_params, hipMemcpyHostToDevice,
+                              b->stream));
+    }
+    if (b->use_graph) {
+        QS_HIP(hipGraphLaunch(want_grads ? b->g_full : b->g_fwd, b->stream));
+    } else {
+        int rc = launch_phase_kernels(b, want_grads);
+        if (rc != QS_OK) return rc;
+    }
+    QS_HIP(hipMemcpyAsync(b->h_energy, b->d_energy, sizeof(double) * 2 * b->circs.size(), hipMemcpyDeviceToHost,
+                          b->stream));
+    if (want_grads && b->num_rot > 0)
+        QS_HIP(hipMemcpyAsync(b->h_gop, b->d_gop, sizeof(double) * 2 * b->num_rot, hipMemcpyDeviceToHost, b->stream));
+    QS_HIP(hipStreamSynchronize(b->stream));
+    if (energies)
+        for (size_t c = 0; c < b->circs.size(); c++) energies[c] = b->h_energy[2 * c];
+    if (want_grads) {
+        for (int p = 0; p < b->total_params; p++) grads[p] = 0.0;
+        // dE/dtheta_p += 2 Re(i scale <lambda|P|phi>) = -2 scale Im<lambda|P|phi>
+        for (int r = 0; r < b->num_rot; r++) grads[b->rot_param[r]] += -2.0 * b->rot_scale[r] * b->h_gop[2 * r + 1];
+    }
+    b->last_run_had_grads = want_grads;
+    return QS_OK;
+}
+
+int qs_batch_get_state(qs_batch *b, int circuit, double *re_im)
+{
+    BCirc *c = circ_at(b, circuit);
+    if (!c) return fail(QS_E_ARG, "no such circuit");
+    if (!b->compiled) return fail(QS_E_PRECOND, "batch is not compiled");
+    if (!re_im) return fail(QS_E_ARG, "null output");
+    QS_HIP(hipStreamSynchronize(b->stream));
+    const uint64_t n = 1ULL << c->n;
+    if (b->precision == QS_C128) {
+        QS_HIP(hipMemcpy(re_im, (double2 *)b->amps + c->amp_off, n * 16, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(2 * n);
+        QS_HIP(hipMemcpy(tmp.data(), (float2 *)b->amps + c->amp_off, n * 8, hipMemcpyDeviceToHost));
+        for (uint64_t i = 0; i < 2 * n; i++) re_im[i] = tmp[i];
+    }
+    return QS_OK;
+}
+
+int qs_batch_stats(const qs_batch *b, int *num_circuits, int *num_steps, uint64_t *total_amps,
+                   uint64_t *logical_updates)
+{
+    if (!b) return fail(QS_E_ARG, "null batch");
+    if (num_circuits) *num_circuits = (int)b->circs.size();
+    if (num_steps) *num_steps = (int)b->d_work.size();
+    uint64_t amps = 0, upd = 0;
+    for (const auto &c : b->circs) {
+        amps += 1ULL << c.n;
+        upd += (uint64_t)c.ops.size() << c.n;
+    }
+    if (total_amps) *total_amps = amps;
+    if (logical_updates) *logical_updates = upd;
+    return QS_OK;
+}
+
+}  // extern "C"

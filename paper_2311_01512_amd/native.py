@@ -74,6 +74,17 @@ _SIGS = {
     "qs_circuit_pass_info": [_P, _I, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                              C.POINTER(C.c_int)],
     "qs_circuit_autotune": [_P, _P, _P, _I, C.POINTER(C.c_int), _PD],
+    "qs_batch_create": [_I, _PP],
+    "qs_batch_destroy": [_P],
+    "qs_batch_add_circuit": [_P, _I, _I, C.POINTER(C.c_int)],
+    "qs_batch_add_rotation": [_P, _I, _I, _I, _I, _D],
+    "qs_batch_add_gate1": [_P, _I, _I, _P],
+    "qs_batch_add_cz": [_P, _I, _I, _I],
+    "qs_batch_set_observable": [_P, _I, _P, _P, _I],
+    "qs_batch_compile": [_P, _P, _I],
+    "qs_batch_run": [_P, _P, _P, _P],
+    "qs_batch_get_state": [_P, _I, _P],
+    "qs_batch_stats": [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
 }
 
 for _name, _args in _SIGS.items():
@@ -308,3 +319,69 @@ def qs_circuit_autotune(q, c, candidates):
     check(lib.qs_circuit_autotune(q, c, ptr(cand), cand.size, C.byref(best),
                                   ms.ctypes.data_as(_PD)), "qs_circuit_autotune")
     return best.value, ms
+
+
+# ---- batches -------------------------------------------------------------------
+
+def qs_batch_create(precision):
+    out = C.c_void_p()
+    check(lib.qs_batch_create(precision, C.byref(out)), "qs_batch_create")
+    return out
+
+
+def qs_batch_destroy(b):
+    check(lib.qs_batch_destroy(b), "qs_batch_destroy")
+
+
+def qs_batch_add_circuit(b, num_qubits, num_params):
+    idx = C.c_int()
+    check(lib.qs_batch_add_circuit(b, num_qubits, num_params, C.byref(idx)), "qs_batch_add_circuit")
+    return idx.value
+
+
+def qs_batch_add_rotation(b, circuit, qubit, pauli, param, scale):
+    check(lib.qs_batch_add_rotation(b, circuit, qubit, pauli, param, float(scale)), "qs_batch_add_rotation")
+
+
+def qs_batch_add_gate1(b, circuit, qubit, matrix):
+    _square(matrix, 2, "matrix")
+    m = cmatrix(matrix)
+    check(lib.qs_batch_add_gate1(b, circuit, qubit, ptr(m)), "qs_batch_add_gate1")
+
+
+def qs_batch_add_cz(b, circuit, q1, q2):
+    check(lib.qs_batch_add_cz(b, circuit, q1, q2), "qs_batch_add_cz")
+
+
+def qs_batch_set_observable(b, circuit, paulis, coeffs, num_qubits):
+    p = np.ascontiguousarray(np.asarray(paulis, dtype=np.int32))
+    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+    if p.size != c.size * num_qubits:
+        raise ValueError("need num_terms * num_qubits Pauli codes")
+    check(lib.qs_batch_set_observable(b, circuit, ptr(p), ptr(c), c.size), "qs_batch_set_observable")
+
+
+def qs_batch_compile(b, hip_stream=None, use_graph=True):
+    check(lib.qs_batch_compile(b, hip_stream, int(bool(use_graph))), "qs_batch_compile")
+
+
+def qs_batch_run(b, params, num_circuits, num_params, grads=True):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    if p.size != num_params:
+        raise ValueError(f"expected {num_params} parameters, got {p.size}")
+    e = np.zeros(num_circuits, dtype=np.float64)
+    g = np.zeros(max(1, num_params), dtype=np.float64) if grads else None
+    check(lib.qs_batch_run(b, ptr(p), ptr(e), ptr(g)), "qs_batch_run")
+    return (e, g[:num_params]) if grads else (e, None)
+
+
+def qs_batch_get_state(b, circuit, num_qubits):
+    a = np.empty(1 << num_qubits, dtype=np.complex128)
+    check(lib.qs_batch_get_state(b, circuit, ptr(a)), "qs_batch_get_state")
+    return a
+
+
+def qs_batch_stats(b):
+    nc, ns, ta, lu = C.c_int(), C.c_int(), C.c_uint64(), C.c_uint64()
+    check(lib.qs_batch_stats(b, C.byref(nc), C.byref(ns), C.byref(ta), C.byref(lu)), "qs_batch_stats")
+    return {"num_circuits": nc.value, "num_steps": ns.value, "total_amps": ta.value, "logical_updates": lu.value}

@@ -1,0 +1,153 @@
+"""Batched circuits of uneven size (tile steps through LDS, one launch per
+step across circuits, HIP-graph replays): final states and energies against
+the oracle, adjoint gradients against the oracle's exact parameter-shift
+gradient and against central finite differences."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import TOL, amp_err, banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qs():
+    import paper_2311_01512_amd as pkg
+    return pkg
+
+
+def hea_problem(rng, n, layers, terms=6, extra=False):
+    angles = rng.uniform(0, 2 * np.pi, size=2 * n * layers)
+    ops = synth.circuits.hea_circuit(n, angles, layers)
+    if extra:   # fixed gates and a long-range CZ as well
+        ops = ops[:3] + [{"op": "unitary", "ctrls": (), "targs": (n - 1,), "matrix": synth.haar_unitary(rng, 2)},
+                         {"op": "unitary", "ctrls": (0,), "targs": (n - 1,), "matrix": np.diag([1.0, -1.0])}] + ops[3:]
+    codes, coeffs = synth.random_pauli_sum(rng, n, terms)
+    return {"n": n, "angles": angles, "ops": ops, "codes": codes, "coeffs": coeffs, "layers": layers}
+
+
+def build(qs, probs, prec, use_graph=True):
+    b = qs.Batch(prec)
+    for p in probs:
+        b.add_circuit(p["n"], p["ops"], len(p["angles"]), p["codes"], p["coeffs"])
+    return b.compile(use_graph=use_graph)
+
+
+SIZES = [1, 3, 5, 8, 11, 12, 13, 15, 17]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_batch_states_and_energies(qs, prec):
+    banner(f"batch forward {prec}")
+    rng = np.random.default_rng(41)
+    probs = [hea_problem(rng, n, 2 + (n % 3), extra=(n % 2 == 1)) for n in SIZES]
+    b = build(qs, probs, prec)
+    st = b.stats()
+    assert st["num_circuits"] == len(probs)
+    params = np.concatenate([p["angles"] for p in probs])
+    e, _ = b.run(params, grads=False)
+    for i, p in enumerate(probs):
+        want = oracle.run_ops(oracle.zero_state(p["n"]), p["ops"])
+        assert amp_err(b.state(i), want) < TOL[prec], p["n"]
+        we = oracle.sv_expec_pauli_sum(want, p["codes"], p["coeffs"]).real
+        assert abs(e[i] - we) < TOL[prec] * max(1.0, np.abs(p["coeffs"]).sum()), p["n"]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_batch_gradients_vs_parameter_shift(qs, prec):
+    banner(f"batch gradients {prec}")
+    rng = np.random.default_rng(43)
+    probs = [hea_problem(rng, n, 2, extra=(n == 13)) for n in (2, 4, 7, 13, 14)]
+    b = build(qs, probs, prec)
+    params = np.concatenate([p["angles"] for p in probs])
+    e, g = b.run(params, grads=True)
+    k = 0
+    for i, p in enumerate(probs):
+        m = len(p["angles"])
+        want = oracle.param_shift_gradient(p["n"], p["ops"], p["codes"], p["coeffs"], m)
+        got = g[k:k + m]
+        scale = max(1.0, np.abs(want).max())
+        tol = 1e-10 if prec == "c128" else 1e-4
+        assert np.abs(got - want).max() < tol * scale, (p["n"], np.abs(got - want).max())
+        k += m
+
+
+def test_batch_gradient_matches_finite_differences(qs):
+    rng = np.random.default_rng(47)
+    probs = [hea_problem(rng, 6, 3), hea_problem(rng, 13, 1)]
+    b = build(qs, probs, "c128")
+    params = np.concatenate([p["angles"] for p in probs])
+    _, g = b.run(params, grads=True)
+    h = 1e-5
+    for idx in list(range(0, params.size, 7)):
+        e1, _ = b.run(params + h * np.eye(params.size)[idx], grads=False)
+        e0, _ = b.run(params - h * np.eye(params.size)[idx], grads=False)
+        circ = 0 if idx < len(probs[0]["angles"]) else 1
+        fd = (e1[circ] - e0[circ]) / (2 * h)
+        assert abs(fd - g[idx]) < 1e-6, (idx, fd, g[idx])
+
+
+def test_batch_closed_form_gradient(qs):
+    """RY(a)|0>: <Z> = cos a, dE/da = -sin a."""
+    b = qs.Batch("c128")
+    a = 1.234
+    ops = [{"op": "gadget", "targs": (0,), "paulis": (2,), "theta": -a / 2, "param": 0, "scale": -0.5}]
+    b.add_circuit(1, ops, 1, np.array([[3]]), [1.0])
+    b.compile()
+    e, g = b.run([a])
+    assert abs(e[0] - np.cos(a)) < 1e-14 and abs(g[0] + np.sin(a)) < 1e-14
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_graph_replays_match_eager(qs, prec):
+    """Several graph replays with different parameters, eager work and
+    synchronisations in between; every replay equals the eager launch."""
+    rng = np.random.default_rng(53)
+    probs = [hea_problem(rng, n, 2) for n in (4, 12, 14)]
+    bg = build(qs, probs, prec, use_graph=True)
+    be = build(qs, probs, prec, use_graph=False)
+    for r in range(4):
+        params = rng.uniform(0, 2 * np.pi, size=sum(len(p["angles"]) for p in probs))
+        eg, gg = bg.run(params, grads=(r % 2 == 0))
+        ee, ge = be.run(params, grads=(r % 2 == 0))
+        assert np.array_equal(eg, ee)
+        if gg is not None:
+            assert np.array_equal(gg, ge)
+
+
+def test_config4_reduced(qs):
+    """The 512-circuit workload generator at 6 circuits of 10-12 qubits:
+    energies and all gradients against the oracle."""
+    banner("config4 reduced")
+    probs = synth.config4_batch(num_circuits=6, nmin=10, nmax=12, num_layers=2)
+    b = qs.Batch("c64")
+    for p in probs:
+        b.add_circuit(p["num_qubits"], p["ops"], len(p["angles"]), p["codes"], p["coeffs"])
+    b.compile()
+    params = np.concatenate([p["angles"] for p in probs])
+    e, g = b.run(params)
+    k = 0
+    for i, p in enumerate(probs):
+        n, m = p["num_qubits"], len(p["angles"])
+        psi = oracle.run_ops(oracle.zero_state(n), p["ops"])
+        assert abs(e[i] - oracle.sv_expec_pauli_sum(psi, p["codes"], p["coeffs"]).real) < 1e-4
+        want = oracle.param_shift_gradient(n, p["ops"], p["codes"], p["coeffs"], m)
+        assert np.abs(g[k:k + m] - want).max() < 1e-4 * max(1.0, np.abs(want).max())
+        k += m
+
+
+def test_batch_errors(qs):
+    b = qs.Batch("c64")
+    with pytest.raises(ValueError):
+        b.add_circuit(0, [], 0)
+    c = b.add_circuit(3, [], 1)
+    with pytest.raises(ValueError):
+        qs.native.qs_batch_add_rotation(b._b, c, 3, 1, 0, 1.0)       # qubit out of range
+    with pytest.raises(ValueError):
+        qs.native.qs_batch_add_rotation(b._b, c, 0, 1, 1, 1.0)       # parameter out of range
+    with pytest.raises(ValueError):
+        qs.native.qs_batch_add_cz(b._b, c, 1, 1)
+    with pytest.raises(ValueError):
+        b.run([0.0])                                                  # not compiled
