@@ -44,6 +44,9 @@ def parse():
                          "(the calibration kernel of known traffic), then one application of the "
                          "fused complex64 circuit")
     ap.add_argument("--probe-fuse-k", type=int, default=5)
+    ap.add_argument("--workload", default="circuit28", choices=["circuit28", "density14", "batch512", "sv34"],
+                    help="circuit28 (default, the headline): 28-qubit 500-gate circuit; density14: 14-qubit "
+                         "density matrix; batch512: 512 circuits with energies and gradients; sv34: 34 qubits")
     return ap.parse_args()
 
 
@@ -172,6 +175,142 @@ def pmc_probe(args):
                       "fuse_k": args.probe_fuse_k}), flush=True)
 
 
+def base_line(metric_value, unit, steps, warmup, ms, dtype, workload, extra):
+    d = {"metric": "amplitude-updates/s & %HBM peak; fused FP32 vs plain FP64 at <=1e-5 amp err",
+         "value": metric_value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+         "dtype": dtype, "data": "synthetic seeded inputs (PCG64 generators, counter-hashed states)",
+         "config": {"workload": workload}}
+    d.update(extra)
+    return d
+
+
+def dm_op_kind(op):
+    k = len(op["targs"]) + len(op.get("ctrls", ()))
+    return ("dm_unitary" if op["op"] == "unitary" else "kraus") + f"_{k}q"
+
+
+def bench_density(args, torch, qs, synth):
+    """14-qubit density matrix (Choi vector of 2^28 amplitudes): 300 ops of
+    Haar unitaries, depolarising, damping and random Kraus maps applied as
+    superoperators, then the partial trace over 7 qubits, trace and purity."""
+    n = 14
+    ops, traced = synth.config3_circuit()
+    logical = synth.count_logical_updates(ops, n, density=True)
+    out = {}
+    for prec in ("c128", "c64"):
+        q = qs.Qureg(n, density=True, precision=prec).init_zero()
+        for _ in range(args.warmup):
+            q.run_ops(ops)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in ops]
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(q.stream)
+        for _ in range(args.steps):
+            q.run_ops(ops)
+        t1.record(q.stream)
+        t1.synchronize()
+        step_s = t0.elapsed_time(t1) * 1e-3 / args.steps
+        for op, (a, b) in zip(ops, ev):
+            a.record(q.stream)
+            q.run_ops([op])
+            b.record(q.stream)
+        torch.cuda.synchronize()
+        kinds = {}
+        for op, (a, b) in zip(ops, ev):
+            c = kinds.setdefault(dm_op_kind(op), [0, 0.0, 0])
+            c[0] += 1
+            c[1] += a.elapsed_time(b)
+            c[2] += 1 << (2 * n)          # one pass over the Choi vector
+        ab = 16 if prec == "c128" else 8
+        ta = torch.cuda.Event(enable_timing=True)
+        tb = torch.cuda.Event(enable_timing=True)
+        ta.record(q.stream)
+        red = q.partial_trace(traced)
+        tb.record(q.stream)
+        tb.synchronize()
+        tr, pur = q.trace(), q.purity()
+        out[prec] = {"value": logical / step_s, "ms_per_step": step_s * 1e3,
+                     "roofline": roofline(kinds, ab, n),
+                     "per_kind": per_kernel_table(kinds, ab),
+                     "partial_trace_ms": ta.elapsed_time(tb),
+                     "trace": [tr.real, tr.imag], "purity": [pur.real, pur.imag],
+                     "reduced_trace": red.trace().real, "reduced_purity": red.purity().real}
+        del q, red
+    head = out["c64"]
+    return base_line(head["value"], "amplitude-updates/s", args.steps, args.warmup, head["ms_per_step"],
+                     "c64 (f32)", "14-qubit density matrix (28-qubit Choi vector), 300 seeded ops: Haar 1/2-qubit "
+                     "unitaries, depolarising, damping, random 2-qubit Kraus maps as superoperators; "
+                     "partial trace over 7 qubits, trace, purity",
+                     {"roofline": head["roofline"], "c64": out["c64"], "c128": out["c128"],
+                      "speedup_c64_vs_c128": out["c128"]["ms_per_step"] / out["c64"]["ms_per_step"]})
+
+
+def bench_batch(args, torch, qs, synth):
+    """512 hardware-efficient-ansatz circuits, N ~ U{10..22}, 6 layers, 20-term
+    Pauli-sum energies and adjoint gradients over all angles, one graph replay."""
+    import numpy as np
+    probs = synth.config4_batch()
+    b = qs.Batch("c64")
+    for p in probs:
+        b.add_circuit(p["num_qubits"], p["ops"], len(p["angles"]), p["codes"], p["coeffs"])
+    b.compile()
+    st = b.stats()
+    params = np.concatenate([p["angles"] for p in probs])
+    for _ in range(args.warmup):
+        b.run(params, grads=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e, g = b.run(params, grads=True)
+    full = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run(params, grads=False)
+    fwd = (time.perf_counter() - t0) / args.steps
+    fwd_upd = st["logical_updates"]
+    total = 3 * fwd_upd      # forward, then U^dagger on phi and on lambda
+    return base_line(total / full, "amplitude-updates/s", args.steps, args.warmup, full * 1e3, "c64 (f32)",
+                     "512 statevectors, N ~ U{10..22}, 6-layer hardware-efficient ansatz, 20-term Pauli-sum "
+                     "energy and adjoint gradient over all angles, one HIP-graph replay",
+                     {"circuits": st["num_circuits"], "total_amplitudes": st["total_amps"],
+                      "launch_steps": st["num_steps"], "forward_only_ms": fwd * 1e3,
+                      "forward_updates_per_s": fwd_upd / fwd, "gradients": int(params.size),
+                      "circuits_per_s_with_gradient": st["num_circuits"] / full,
+                      "energy_mean": float(np.mean(e))})
+
+
+def bench_sv34(args, torch, qs, synth):
+    """34-qubit complex64 statevector (2^34 amplitudes, 128 GiB): 200 gates of
+    5-target Haar unitaries with up to 4 controls and Pauli gadgets of weight
+    up to 34, plain per-gate vs fused (k = 6); <Z_0 Z_33> and norm in FP64."""
+    import numpy as np
+    n = 34
+    ops = synth.config5_circuit()
+    logical = synth.count_logical_updates(ops, n)
+    q = qs.Qureg(n, precision="c64").init_hashed(5)
+    res = {}
+    norm0 = q.total_prob()
+    for label, k in (("plain_c64", 0), ("fused_c64", 6)):
+        circ = qs.Circuit(n, ops).compile(k, "c64")
+        t = time_steps(circ, q, 1, torch)
+        kinds = time_passes(circ, q, torch)
+        res[label] = {"value": logical / t, "ms_per_step": t * 1e3, "passes": circ.stats()["num_passes"],
+                      "roofline": roofline(kinds, 8, n), "per_kernel": per_kernel_table(kinds, 8)}
+        del circ
+    zz = np.zeros((1, n), np.int32)
+    zz[0, 0] = zz[0, n - 1] = 3
+    ezz = q.expec_pauli_sum(zz, [1.0])
+    norm1 = q.total_prob()
+    head = res["fused_c64"]
+    return base_line(head["value"], "amplitude-updates/s", 1, 0, head["ms_per_step"], "c64 (f32)",
+                     "34-qubit complex64 statevector (128 GiB), 200 seeded gates: 5-target Haar unitaries with "
+                     "0-4 controls and Pauli gadgets of weight 1-34",
+                     {"roofline": head["roofline"], "fused_c64": res["fused_c64"], "plain_c64": res["plain_c64"],
+                      "zz_0_33": [ezz.real, ezz.imag], "norm_before": norm0,
+                      "norm_after_4_circuit_passes": norm1, "relative_norm_drift": abs(norm1 - norm0) / norm0})
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -181,6 +320,12 @@ def main():
         pmc_probe(args)
         return
     import torch
+    if args.workload != "circuit28":
+        import synth
+        import paper_2311_01512_amd as qs
+        fn = {"density14": bench_density, "batch512": bench_batch, "sv34": bench_sv34}[args.workload]
+        print(json.dumps(fn(args, torch, qs, synth)), flush=True)
+        return
     import synth
     import paper_2311_01512_amd as qs
 
