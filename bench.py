@@ -219,10 +219,12 @@ def bench_density(args, torch, qs, synth):
         torch.cuda.synchronize()
         kinds = {}
         for op, (a, b) in zip(ops, ev):
-            c = kinds.setdefault(dm_op_kind(op), [0, 0.0, 0])
+            c = kinds.setdefault(dm_op_kind(op), [0, 0.0, 0, 0])
+            k = len(op["targs"]) + len(op.get("ctrls", ()))
             c[0] += 1
             c[1] += a.elapsed_time(b)
-            c[2] += 1 << (2 * n)          # one pass over the Choi vector
+            c[2] += 1 << (2 * n)                          # one pass over the Choi vector
+            c[3] += 8 * (1 << (2 * k)) * (1 << (2 * n))   # 4^k x 4^k superoperator
         ab = 16 if prec == "c128" else 8
         ta = torch.cuda.Event(enable_timing=True)
         tb = torch.cuda.Event(enable_timing=True)
