@@ -723,6 +723,9 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
     }
     b->total_amps = off;
     b->total_params = poff;
+    // per-amplitude launches cover the whole batch in one dispatch, whose
+    // size in work-items is a 32-bit number
+    if (off > 0xFFFFFFFFull - 255) return fail(QS_E_ARG, "batch holds more than 2^32 amplitudes");
 
     // steps, operators, rotation slots and gradient partials
     std::vector<DStep> steps;

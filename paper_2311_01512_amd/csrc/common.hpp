@@ -129,6 +129,9 @@ bool valid_qubits(const int *qs, int count, int n, std::string &why);
 // only for work beyond max_blocks * block.
 inline unsigned grid_for(uint64_t work, int block, uint64_t max_blocks = 1ull << 30)
 {
+    // a dispatch holds its grid size in work-items as a 32-bit number
+    const uint64_t dispatch_cap = 0xFFFFFFFFull / (uint64_t)block;
+    if (max_blocks > dispatch_cap) max_blocks = dispatch_cap;
     uint64_t b = (work + block - 1) / block;
     if (b > max_blocks) b = max_blocks;
     if (b < 1) b = 1;

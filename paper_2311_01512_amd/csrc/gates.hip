@@ -321,7 +321,8 @@ static int launch_mfma(qs_qureg *q, uint64_t num_groups, const InsertPlan &plan,
     const uint64_t tiles = num_groups / 16;   // num_groups is a multiple of 16 (checked by the caller)
     const uint64_t waves_per_block = 4;
     uint64_t blocks = (tiles + waves_per_block - 1) / waves_per_block;
-    const uint64_t cap = mfma_block_cap(K);
+    uint64_t cap = mfma_block_cap(K);
+    if (cap > 0xFFFFFFFFull / 256) cap = 0xFFFFFFFFull / 256;   // 32-bit dispatch size in work-items
     if (blocks > cap) blocks = cap;
     hipLaunchKernelGGL((k_dense_mfma<K>), dim3((unsigned)blocks), dim3(256), bytes, q->stream, (float2 *)q->amps,
                        tiles, plan, ctrl_mask, tb, (const f32x4 *)dev);
