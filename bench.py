@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=28)
     ap.add_argument("--gates", type=int, default=500)
-    ap.add_argument("--fuse-candidates", default="0,3,4,5,6")
+    ap.add_argument("--fuse-candidates", default="0,4,5,10,11,12,13",
+                    help="fusion widths the autotuner tries: 0 plain, 2-6 dense blocks, 8-14 LDS tiles")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -58,6 +59,8 @@ def kernel_name(info, real):
         return f"k_gadget_diag<{real}>"
     if k == "dense_mfma":
         return f"k_dense_mfma<{info['num_targs']}>"
+    if k == "tile":
+        return f"k_tile_step<{real}>"
     return f"k_gate<{real}, {info['num_targs']}>"
 
 
@@ -108,6 +111,8 @@ def time_passes(circ, q, torch):
     for info, (a, b) in zip(infos, ev):
         name = kernel_name(info, real)
         amps = 1 << (n - info["num_ctrls"])
+        if info["kernel"] == "tile":
+            amps = 1 << n          # one read and one write of the whole state per step
         flops = 8 * (1 << info["num_targs"]) * amps if info["kernel"].startswith("dense") else 0
         c = out.setdefault(name, [0, 0.0, 0, 0])
         c[0] += 1

@@ -1,44 +1,12 @@
 // Recorded circuits: the plain per-gate pass list, or gates fused into dense
 // k-qubit blocks (FP64 products on the host), with every pass's matrix kept
 // on the device in the layout of the kernel that runs it.
-#include "common.hpp"
+#include "circuit.hpp"
 
 #include <algorithm>
 #include <cmath>
 
 namespace qs {
-
-struct CircOp {
-    bool gadget;
-    std::vector<int> ctrls, targs;    // unitary: controls, targets in matrix order
-    std::vector<cd> M;                // unitary matrix, row-major 2^nt x 2^nt
-    std::vector<int> paulis;          // gadget: codes per target
-    double theta;
-    std::vector<int> support() const
-    {
-        std::vector<int> s;
-        if (gadget) {
-            for (size_t k = 0; k < targs.size(); k++)
-                if (paulis[k] != 0) s.push_back(targs[k]);
-        } else {
-            s = ctrls;
-            s.insert(s.end(), targs.begin(), targs.end());
-        }
-        return s;
-    }
-};
-
-struct Pass {
-    bool gadget;
-    std::vector<int> ctrls, sorted_targs;
-    std::vector<cd> Ms;               // dense matrix in ascending target order
-    std::vector<int> gtargs, paulis;  // gadget pass
-    double theta;
-    int kernel;
-    size_t dev_offset;                // into the circuit's device buffer
-    bool has_dev;
-    int members;
-};
 
 // Dense matrix of a gadget exp(i theta P) on its non-identity targets, in
 // the order of those targets: cos(theta) 1 + i sin(theta) P, with
@@ -120,21 +88,10 @@ static std::vector<cd> matmul(const std::vector<cd> &A, const std::vector<cd> &B
 
 using namespace qs;
 
-struct qs_circuit {
-    int num_qubits;
-    std::vector<CircOp> ops;
-    std::vector<Pass> passes;
-    bool compiled = false;
-    int precision = -1;
-    int fuse_k = 0;
-    void *dev = nullptr;
-    size_t dev_bytes = 0;
-    int device = -1;
-};
 
 namespace qs {
 
-static Pass single_pass(const CircOp &op)
+Pass single_pass(const CircOp &op)
 {
     Pass p{};
     p.members = 1;
@@ -274,17 +231,29 @@ int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision)
 {
     if (!c) return fail(QS_E_ARG, "null circuit");
     if (precision != QS_C64 && precision != QS_C128) return fail(QS_E_ARG, "bad precision");
-    if (fuse_k != 0 && (fuse_k < 2 || fuse_k > 6)) return fail(QS_E_ARG, "fuse_k is 0 or 2..6");
+    const bool tiles = fuse_k >= 8 && fuse_k <= kTileDimMax;
+    if (fuse_k != 0 && !tiles && (fuse_k < 2 || fuse_k > 6))
+        return fail(QS_E_ARG, "fuse_k is 0, 2..6 (dense blocks) or 8..14 (LDS tiles)");
+    if (tiles && fuse_k > tile_dim_limit(precision))
+        return fail(QS_E_ARG, "tile of 2^" + std::to_string(fuse_k) + " amplitudes exceeds the LDS of a block");
     c->passes.clear();
     if (fuse_k == 0) {
         for (const auto &op : c->ops) c->passes.push_back(single_pass(op));
+    } else if (tiles) {
+        plan_tiles(c, fuse_k, precision);
     } else {
         fuse(c, fuse_k);
     }
-    // device copies of every dense pass's matrix, in its kernel's layout
+    // device copies of every pass's tables, in its kernel's layout
     size_t total = 0;
     for (auto &p : c->passes) {
         if (p.gadget) continue;
+        if (p.tile) {
+            p.has_dev = true;
+            p.dev_offset = total;
+            total += (tile_pass_bytes(p, precision) + 255) & ~size_t(255);
+            continue;
+        }
         const int nt = (int)p.sorted_targs.size();
         p.kernel = choose_dense_kernel(precision, nt);
         const size_t b = dense_matrix_bytes(precision, nt, p.kernel);
@@ -298,9 +267,12 @@ int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision)
     }
     if (total > 0) {
         std::vector<unsigned char> host(total, 0);
-        for (auto &p : c->passes)
-            if (!p.gadget && p.has_dev)
+        for (auto &p : c->passes) {
+            if (p.tile)
+                pack_tile_pass(p, precision, host.data() + p.dev_offset);
+            else if (!p.gadget && p.has_dev)
                 pack_dense(precision, (int)p.sorted_targs.size(), p.kernel, p.Ms, host.data() + p.dev_offset);
+        }
         if (hipMalloc(&c->dev, total) != hipSuccess) {
             (void)hipGetLastError();
             c->dev = nullptr;
@@ -330,7 +302,8 @@ int qs_circuit_stats(const qs_circuit *c, int *num_ops, int *num_passes, uint64_
     }
     if (blocks_by_width) {
         for (int i = 0; i < 7; i++) blocks_by_width[i] = 0;
-        for (const auto &p : c->passes) blocks_by_width[p.gadget ? 0 : (int)p.sorted_targs.size()]++;
+        for (const auto &p : c->passes)
+            if (!p.tile) blocks_by_width[p.gadget ? 0 : (int)p.sorted_targs.size()]++;
     }
     return QS_OK;
 }
@@ -382,7 +355,11 @@ int qs_circuit_pass_info(const qs_circuit *c, int index, int *kernel, int *num_t
     if (index < 0 || index >= (int)c->passes.size()) return fail(QS_E_ARG, "pass index out of range");
     const Pass &p = c->passes[index];
     int k, nt, nc;
-    if (p.gadget) {
+    if (p.tile) {
+        k = 4;
+        nt = p.tile_d;
+        nc = 0;
+    } else if (p.gadget) {
         bool xy = false;
         nt = 0;
         for (int code : p.paulis) {
@@ -417,7 +394,9 @@ int qs_apply_circuit_passes(qs_qureg *q, qs_circuit *c, int first, int count)
     for (int pi = first; pi < first + count; pi++) {
         const Pass &p = c->passes[pi];
         int rc;
-        if (p.gadget) {
+        if (p.tile) {
+            rc = launch_tile_pass(q, p, (const unsigned char *)c->dev + p.dev_offset);
+        } else if (p.gadget) {
             rc = apply_raw_gadget(q, p.gtargs, p.paulis, p.theta);
         } else {
             const void *dev = p.has_dev ? (const void *)((const unsigned char *)c->dev + p.dev_offset) : nullptr;

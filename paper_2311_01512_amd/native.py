@@ -302,7 +302,7 @@ def qs_apply_circuit_passes(q, c, first, count):
     check(lib.qs_apply_circuit_passes(q, c, first, count), "qs_apply_circuit_passes")
 
 
-PASS_KERNELS = {0: "gadget_pairs", 1: "gadget_diag", 2: "dense_vector", 3: "dense_mfma"}
+PASS_KERNELS = {0: "gadget_pairs", 1: "gadget_diag", 2: "dense_vector", 3: "dense_mfma", 4: "tile"}
 
 
 def qs_circuit_pass_info(c, index):

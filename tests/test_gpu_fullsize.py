@@ -86,7 +86,7 @@ def check_cosets(torch, q, n_bits, seed, Q, ops, rng, num_cosets, tol, density=F
     return worst
 
 
-@pytest.mark.parametrize("path", [("c128", 0), ("c64", 4), ("c64", 6)])
+@pytest.mark.parametrize("path", [("c128", 0), ("c64", 4), ("c64", 6), ("c64", 12), ("c128", 11)])
 def test_28_qubits_sampled(qs, path):
     import torch
     prec, k = path
@@ -229,7 +229,7 @@ def test_34_qubits_sampled(qs):
     Q = sorted([0, 1, 2, 3, 33, 32, 31] + [int(x) for x in rng.choice(np.arange(4, 31), size=5, replace=False)])
     ops = ops_on(rng, Q, 12, max_targets=5, max_ctrls=4, gadget_weight=12)
     q = qs.Qureg(N, precision="c64")
-    for k in (6, 0):
+    for k in (6, 0, 12):
         banner(f"34 qubits fuse_k={k}")
         q.init_hashed(seed)
         n0 = q.total_prob()

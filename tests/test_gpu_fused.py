@@ -49,7 +49,7 @@ def test_mfma_nonunitary_many_tiles(qs):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("k", [0, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("k", [0, 2, 3, 4, 5, 6, 8, 10, 11, 12])
 def test_fused_circuit_parity(qs, prec, k):
     banner(f"fused circuit k={k} {prec}")
     N = 14
@@ -64,14 +64,20 @@ def test_fused_circuit_parity(qs, prec, k):
         assert st["num_passes"] == len(ops)
     else:
         assert st["num_passes"] < len(ops)
-        assert max(i for i, w in enumerate(st["passes_by_width"]) if w) <= k
+        if k <= 6:
+            assert max(i for i, w in enumerate(st["passes_by_width"]) if w) <= k
+        else:
+            kinds = [circ.pass_info(i)["kernel"] for i in range(st["num_passes"])]
+            assert kinds.count("tile") >= 1
+            assert all(circ.pass_info(i)["num_targs"] <= k for i in range(st["num_passes"])
+                       if kinds[i] == "tile")
     q = qs.Qureg(N, precision=prec).set_amps(psi)
     circ.apply(q)
     want = oracle.run_ops(psi.copy(), ops)
     assert amp_err(q.get_amps(), want) < TOL[prec]
 
 
-@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("k", [2, 3, 4, 6, 7, 8])
 def test_fusion_respects_order(qs, k):
     """Dense non-commuting gates on overlapping qubits, interleaved with gates
     elsewhere: blocks may only absorb ops that commute with what they skip."""
