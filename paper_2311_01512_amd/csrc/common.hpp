@@ -177,6 +177,9 @@ int mfma_preference();
 // Upper bound on the MFMA kernel's grid for a k-target gate.
 uint64_t mfma_block_cap(int k);
 
+// Threads per block of the LDS tile engine (power of two, 64..1024).
+int tile_block_size();
+
 // Key of a recorded circuit's contents (circuit.hip).
 uint64_t circuit_fingerprint(const qs_circuit *c);
 int circuit_num_qubits(const qs_circuit *c);

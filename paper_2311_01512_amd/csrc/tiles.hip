@@ -298,24 +298,25 @@ __device__ void tile_gadget(C2<R> *v, int d, const TOp &op, uint64_t base)
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_tile_step(C2<R> *__restrict__ a, TileArgs ta, const TOp *__restrict__ tops,
-                                                    const C2<R> *__restrict__ mats)
+__global__ __launch_bounds__(1024) void k_tile_step(C2<R> *__restrict__ a, TileArgs ta, const TOp *__restrict__ tops,
+                                                     const C2<R> *__restrict__ mats)
 {
     extern __shared__ unsigned char lds_raw[];
     C2<R> *v = reinterpret_cast<C2<R> *>(lds_raw);
     const int T = 1 << ta.d;
-    // coordinates c = threadIdx.x + 256 r: the address is linear in c
+    const int lb = 31 - __clz(blockDim.x);   // block size is a power of two
+    // coordinates c = threadIdx.x + blockDim.x r: the address is linear in c
     uint64_t xt = 0;
-    for (int k = 0; k < 8 && k < ta.d; k++)
+    for (int k = 0; k < lb && k < ta.d; k++)
         if ((threadIdx.x >> k) & 1) xt ^= ta.w[k];
     for (uint64_t tile = blockIdx.x; tile < ta.num_tiles; tile += gridDim.x) {
         const uint64_t base = insert_zeros(tile, ta.plan);
-        for (int r = 0; (r << 8) < T; r++) {
-            const int c = (int)threadIdx.x + (r << 8);
+        for (int r = 0; (r << lb) < T; r++) {
+            const int c = (int)threadIdx.x + (r << lb);
             if (c < T) {
                 uint64_t x = xt;
-                for (int k = 8; k < ta.d; k++)
-                    if ((r >> (k - 8)) & 1) x ^= ta.w[k];
+                for (int k = lb; k < ta.d; k++)
+                    if ((r >> (k - lb)) & 1) x ^= ta.w[k];
                 v[c] = a[base ^ x];
             }
         }
@@ -332,12 +333,12 @@ __global__ __launch_bounds__(256) void k_tile_step(C2<R> *__restrict__ a, TileAr
             }
             __syncthreads();
         }
-        for (int r = 0; (r << 8) < T; r++) {
-            const int c = (int)threadIdx.x + (r << 8);
+        for (int r = 0; (r << lb) < T; r++) {
+            const int c = (int)threadIdx.x + (r << lb);
             if (c < T) {
                 uint64_t x = xt;
-                for (int k = 8; k < ta.d; k++)
-                    if ((r >> (k - 8)) & 1) x ^= ta.w[k];
+                for (int k = lb; k < ta.d; k++)
+                    if ((r >> (k - lb)) & 1) x ^= ta.w[k];
                 a[base ^ x] = v[c];
             }
         }
@@ -358,12 +359,13 @@ int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev)
     const unsigned char *mats = d + (((p.tops.size() * sizeof(TOp)) + 255) & ~size_t(255));
     const size_t ab = q->precision == QS_C64 ? sizeof(float2) : sizeof(double2);
     const size_t lds = ((size_t)1 << p.tile_d) * ab;
-    const unsigned grid = grid_for(ta.num_tiles, 1, 0xFFFFFFFFull / 256);
+    const unsigned block = (unsigned)tile_block_size();
+    const unsigned grid = grid_for(ta.num_tiles, 1, 0xFFFFFFFFull / block);
     if (q->precision == QS_C64)
-        hipLaunchKernelGGL(k_tile_step<float>, dim3(grid), dim3(256), lds, q->stream, (float2 *)q->amps, ta,
+        hipLaunchKernelGGL(k_tile_step<float>, dim3(grid), dim3(block), lds, q->stream, (float2 *)q->amps, ta,
                            (const TOp *)d, (const float2 *)mats);
     else
-        hipLaunchKernelGGL(k_tile_step<double>, dim3(grid), dim3(256), lds, q->stream, (double2 *)q->amps, ta,
+        hipLaunchKernelGGL(k_tile_step<double>, dim3(grid), dim3(block), lds, q->stream, (double2 *)q->amps, ta,
                            (const TOp *)d, (const double2 *)mats);
     QS_LAUNCH_CHECK();
     return QS_OK;

@@ -36,6 +36,19 @@ uint64_t mfma_block_cap(int)
     return cap;
 }
 
+int tile_block_size()
+{
+    static const int bs = [] {
+        const char *e = std::getenv("QS_TILE_BLOCK");
+        if (e) {
+            const int v = std::atoi(e);
+            if (v == 64 || v == 128 || v == 256 || v == 512 || v == 1024) return v;
+        }
+        return 256;
+    }();
+    return bs;
+}
+
 // (qubits, precision, circuit fingerprint) -> chosen fusion width
 using TuneKey = std::tuple<int, int, uint64_t>;
 static std::map<TuneKey, int> g_tuned;
