@@ -177,7 +177,8 @@ int mfma_preference();
 // Upper bound on the MFMA kernel's grid for a k-target gate.
 uint64_t mfma_block_cap(int k);
 
-// Threads per block of the LDS tile engine (power of two, 64..1024).
+// Threads per block forced for the LDS tile engine (QS_TILE_BLOCK), 0 if
+// the launcher chooses.
 int tile_block_size();
 
 // Key of a recorded circuit's contents (circuit.hip).

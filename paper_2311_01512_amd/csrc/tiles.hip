@@ -223,6 +223,11 @@ void pack_tile_pass(const Pass &p, int precision, void *out)
 }
 
 // ---- kernel -------------------------------------------------------------------------------
+//
+// EL = log2(tile entries per thread).  With EL fixed at compile time every
+// per-operator loop is unrolled: a thread first loads all of its pairs or
+// groups from LDS, then computes and stores them, so the LDS round trips of
+// one operator overlap instead of running one after another.
 
 struct TileArgs {
     int d;
@@ -232,118 +237,179 @@ struct TileArgs {
     uint64_t num_tiles;
 };
 
-template <typename R, int NT>
+template <int NT>
+__device__ __forceinline__ int spread_group(int g, const TOp &op)
+{
+#pragma unroll
+    for (int i = 0; i < NT; i++) {
+        const int lo = (1 << op.pos[i]) - 1;
+        g = (g & lo) | ((g & ~lo) << 1);
+    }
+    return g;
+}
+
+template <int NT>
+__device__ __forceinline__ int local_member(int cb, int l, const TOp &op)
+{
+#pragma unroll
+    for (int i = 0; i < NT; i++)
+        if ((l >> i) & 1) cb |= 1 << op.pos[i];
+    return cb;
+}
+
+template <typename R, int NT, int EL>
 __device__ void tile_dense(C2<R> *v, int d, const TOp &op, uint64_t base, const C2<R> *__restrict__ mat)
 {
     constexpr int D = 1 << NT;
+    constexpr int PER = (EL >= NT) ? (1 << (EL - NT)) : 1;   // groups per thread
     const int groups = 1 << (d - NT);
-    for (int g = threadIdx.x; g < groups; g += blockDim.x) {
-        int cb = g;
+    C2<R> m[D * D];
 #pragma unroll
-        for (int i = 0; i < NT; i++) {
-            const int lo = (1 << op.pos[i]) - 1;
-            cb = (cb & lo) | ((cb & ~lo) << 1);
-        }
-        bool on = true;
+    for (int k = 0; k < D * D; k++) m[k] = mat[k];
+    int cb[PER];
+    bool on[PER];
+    C2<R> x[PER][D];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int g = threadIdx.x + u * blockDim.x;
+        cb[u] = spread_group<NT>(g, op);
+        bool ok = g < groups;
         for (int i = 0; i < op.nc; i++)
-            on &= (((base >> op.cq[i]) & 1ULL) ^ (uint64_t)(__popc(cb & op.cm[i]) & 1)) != 0;
-        if (!on) continue;
-        C2<R> x[D];
+            ok &= (((base >> op.cq[i]) & 1ULL) ^ (uint64_t)(__popc(cb[u] & op.cm[i]) & 1)) != 0;
+        on[u] = ok;
+        if (ok) {
 #pragma unroll
-        for (int l = 0; l < D; l++) {
-            int c = cb;
-#pragma unroll
-            for (int i = 0; i < NT; i++)
-                if ((l >> i) & 1) c |= 1 << op.pos[i];
-            x[l] = v[c];
+            for (int l = 0; l < D; l++) x[u][l] = v[local_member<NT>(cb[u], l, op)];
         }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        if (!on[u]) continue;
 #pragma unroll
         for (int j = 0; j < D; j++) {
             C2<R> acc = mk<R>(R(0), R(0));
 #pragma unroll
-            for (int l = 0; l < D; l++) cmac<R>(acc, mat[j * D + l], x[l]);
-            int c = cb;
-#pragma unroll
-            for (int i = 0; i < NT; i++)
-                if ((j >> i) & 1) c |= 1 << op.pos[i];
-            v[c] = acc;
+            for (int l = 0; l < D; l++) cmac<R>(acc, m[j * D + l], x[u][l]);
+            v[local_member<NT>(cb[u], j, op)] = acc;
         }
     }
 }
 
-template <typename R>
+template <typename R, int EL>
 __device__ void tile_gadget(C2<R> *v, int d, const TOp &op, uint64_t base)
 {
-    const int T = 1 << d;
     const int sb = __popcll(base & op.yz) & 1;
     const R cs = (R)op.cs, cr = (R)op.cre, ci = (R)op.cim;
     if (op.flip == 0) {
-        for (int c = threadIdx.x; c < T; c += blockDim.x) {
-            const R s = ((sb ^ __popc((unsigned)c & op.yzm)) & 1) ? R(-1) : R(1);
-            const C2<R> a = v[c];
-            v[c] = mk<R>(cs * a.x + s * (cr * a.x - ci * a.y), cs * a.y + s * (cr * a.y + ci * a.x));
+        constexpr int PER = 1 << EL;
+        const int T = 1 << d;
+        C2<R> x[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int c = threadIdx.x + u * blockDim.x;
+            if (c < T) x[u] = v[c];
+        }
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int c = threadIdx.x + u * blockDim.x;
+            if (c < T) {
+                const R s = ((sb ^ __popc((unsigned)c & op.yzm)) & 1) ? R(-1) : R(1);
+                const C2<R> a = x[u];
+                v[c] = mk<R>(cs * a.x + s * (cr * a.x - ci * a.y), cs * a.y + s * (cr * a.y + ci * a.x));
+            }
         }
         return;
     }
+    constexpr int PER = (EL >= 1) ? (1 << (EL - 1)) : 1;
+    const int np = 1 << (d - 1);
     const int hb = 31 - __clz(op.flip);
     const int lo = (1 << hb) - 1;
-    for (int p = threadIdx.x; p < (T >> 1); p += blockDim.x) {
-        const int c0 = (p & lo) | ((p & ~lo) << 1), c1 = c0 ^ (int)op.flip;
-        const R s0 = ((sb ^ __popc((unsigned)c0 & op.yzm)) & 1) ? R(-1) : R(1);
+    int c0[PER];
+    C2<R> a0[PER], a1[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int p = threadIdx.x + u * blockDim.x;
+        c0[u] = (p & lo) | ((p & ~lo) << 1);
+        if (p < np) {
+            a0[u] = v[c0[u]];
+            a1[u] = v[c0[u] ^ (int)op.flip];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int p = threadIdx.x + u * blockDim.x;
+        if (p >= np) continue;
+        const int c1 = c0[u] ^ (int)op.flip;
+        const R s0 = ((sb ^ __popc((unsigned)c0[u] & op.yzm)) & 1) ? R(-1) : R(1);
         const R s1 = ((sb ^ __popc((unsigned)c1 & op.yzm)) & 1) ? R(-1) : R(1);
-        const C2<R> a0 = v[c0], a1 = v[c1];
-        v[c0] = mk<R>(cs * a0.x + s1 * (cr * a1.x - ci * a1.y), cs * a0.y + s1 * (cr * a1.y + ci * a1.x));
-        v[c1] = mk<R>(cs * a1.x + s0 * (cr * a0.x - ci * a0.y), cs * a1.y + s0 * (cr * a0.y + ci * a0.x));
+        const C2<R> x0 = a0[u], x1 = a1[u];
+        v[c0[u]] = mk<R>(cs * x0.x + s1 * (cr * x1.x - ci * x1.y), cs * x0.y + s1 * (cr * x1.y + ci * x1.x));
+        v[c1] = mk<R>(cs * x1.x + s0 * (cr * x0.x - ci * x0.y), cs * x1.y + s0 * (cr * x0.y + ci * x0.x));
     }
 }
 
-template <typename R>
+template <typename R, int EL>
 __global__ __launch_bounds__(1024) void k_tile_step(C2<R> *__restrict__ a, TileArgs ta, const TOp *__restrict__ tops,
                                                      const C2<R> *__restrict__ mats)
 {
     extern __shared__ unsigned char lds_raw[];
     C2<R> *v = reinterpret_cast<C2<R> *>(lds_raw);
+    constexpr int PER = 1 << EL;
     const int T = 1 << ta.d;
     const int lb = 31 - __clz(blockDim.x);   // block size is a power of two
-    // coordinates c = threadIdx.x + blockDim.x r: the address is linear in c
+    // coordinates c = threadIdx.x + blockDim.x u: the address is linear in c
     uint64_t xt = 0;
     for (int k = 0; k < lb && k < ta.d; k++)
         if ((threadIdx.x >> k) & 1) xt ^= ta.w[k];
+    uint64_t xu[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        uint64_t x = xt;
+        for (int k = lb; k < ta.d; k++)
+            if ((u >> (k - lb)) & 1) x ^= ta.w[k];
+        xu[u] = x;
+    }
     for (uint64_t tile = blockIdx.x; tile < ta.num_tiles; tile += gridDim.x) {
         const uint64_t base = insert_zeros(tile, ta.plan);
-        for (int r = 0; (r << lb) < T; r++) {
-            const int c = (int)threadIdx.x + (r << lb);
-            if (c < T) {
-                uint64_t x = xt;
-                for (int k = lb; k < ta.d; k++)
-                    if ((r >> (k - lb)) & 1) x ^= ta.w[k];
-                v[c] = a[base ^ x];
-            }
-        }
+#pragma unroll
+        for (int u = 0; u < PER; u++)
+            if ((int)threadIdx.x + (u << lb) < T) v[threadIdx.x + (u << lb)] = a[base ^ xu[u]];
         __syncthreads();
         for (int o = 0; o < ta.nops; o++) {
             const TOp &op = tops[o];
             if (op.kind == 1) {
-                tile_gadget<R>(v, ta.d, op, base);
+                tile_gadget<R, EL>(v, ta.d, op, base);
             } else {
                 const C2<R> *m = mats + op.mat;
-                if (op.nt == 1) tile_dense<R, 1>(v, ta.d, op, base, m);
-                else if (op.nt == 2) tile_dense<R, 2>(v, ta.d, op, base, m);
-                else tile_dense<R, 3>(v, ta.d, op, base, m);
+                if (op.nt == 1) tile_dense<R, 1, EL>(v, ta.d, op, base, m);
+                else if (op.nt == 2) tile_dense<R, 2, EL>(v, ta.d, op, base, m);
+                else tile_dense<R, 3, EL>(v, ta.d, op, base, m);
             }
             __syncthreads();
         }
-        for (int r = 0; (r << lb) < T; r++) {
-            const int c = (int)threadIdx.x + (r << lb);
-            if (c < T) {
-                uint64_t x = xt;
-                for (int k = lb; k < ta.d; k++)
-                    if ((r >> (k - lb)) & 1) x ^= ta.w[k];
-                a[base ^ x] = v[c];
-            }
-        }
+#pragma unroll
+        for (int u = 0; u < PER; u++)
+            if ((int)threadIdx.x + (u << lb) < T) a[base ^ xu[u]] = v[threadIdx.x + (u << lb)];
         __syncthreads();
     }
+}
+
+template <typename R>
+static int launch_tile_r(qs_qureg *q, int el, unsigned grid, unsigned block, size_t lds, const TileArgs &ta,
+                         const TOp *tops, const C2<R> *mats)
+{
+    C2<R> *amps = (C2<R> *)q->amps;
+    switch (el) {
+    case 0: hipLaunchKernelGGL((k_tile_step<R, 0>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
+    case 1: hipLaunchKernelGGL((k_tile_step<R, 1>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
+    case 2: hipLaunchKernelGGL((k_tile_step<R, 2>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
+    case 3: hipLaunchKernelGGL((k_tile_step<R, 3>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
+    case 4: hipLaunchKernelGGL((k_tile_step<R, 4>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
+    case 5: hipLaunchKernelGGL((k_tile_step<R, 5>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
+    default: hipLaunchKernelGGL((k_tile_step<R, 6>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
+    }
+    QS_LAUNCH_CHECK();
+    return QS_OK;
 }
 
 int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev)
@@ -359,16 +425,17 @@ int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev)
     const unsigned char *mats = d + (((p.tops.size() * sizeof(TOp)) + 255) & ~size_t(255));
     const size_t ab = q->precision == QS_C64 ? sizeof(float2) : sizeof(double2);
     const size_t lds = ((size_t)1 << p.tile_d) * ab;
-    const unsigned block = (unsigned)tile_block_size();
+    // threads per block: 8 tile entries per thread (measured best), between
+    // 64 and 1024 threads, unless QS_TILE_BLOCK overrides it
+    int lb = std::min(10, std::max(6, p.tile_d - 3));
+    if (const int forced = tile_block_size()) lb = 31 - __builtin_clz((unsigned)forced);
+    while (p.tile_d - lb > 4 && lb < 10) lb++;
+    const unsigned block = 1u << lb;
+    const int el = std::max(0, p.tile_d - lb);
     const unsigned grid = grid_for(ta.num_tiles, 1, 0xFFFFFFFFull / block);
     if (q->precision == QS_C64)
-        hipLaunchKernelGGL(k_tile_step<float>, dim3(grid), dim3(block), lds, q->stream, (float2 *)q->amps, ta,
-                           (const TOp *)d, (const float2 *)mats);
-    else
-        hipLaunchKernelGGL(k_tile_step<double>, dim3(grid), dim3(block), lds, q->stream, (double2 *)q->amps, ta,
-                           (const TOp *)d, (const double2 *)mats);
-    QS_LAUNCH_CHECK();
-    return QS_OK;
+        return launch_tile_r<float>(q, el, grid, block, lds, ta, (const TOp *)d, (const float2 *)mats);
+    return launch_tile_r<double>(q, el, grid, block, lds, ta, (const TOp *)d, (const double2 *)mats);
 }
 
 }  // namespace qs

@@ -44,7 +44,7 @@ int tile_block_size()
             const int v = std::atoi(e);
             if (v == 64 || v == 128 || v == 256 || v == 512 || v == 1024) return v;
         }
-        return 256;
+        return 0;   // sized by the launcher
     }();
     return bs;
 }
