@@ -233,7 +233,7 @@ int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision)
     if (precision != QS_C64 && precision != QS_C128) return fail(QS_E_ARG, "bad precision");
     const bool tiles = fuse_k >= 8 && fuse_k <= kTileDimMax;
     if (fuse_k != 0 && !tiles && (fuse_k < 2 || fuse_k > 6))
-        return fail(QS_E_ARG, "fuse_k is 0, 2..6 (dense blocks) or 8..14 (LDS tiles)");
+        return fail(QS_E_ARG, "fuse_k is 0, 2..6 (dense blocks) or 8.." + std::to_string(kTileDimMax) + " (tiles)");
     if (tiles && fuse_k > tile_dim_limit(precision))
         return fail(QS_E_ARG, "tile of 2^" + std::to_string(fuse_k) + " amplitudes exceeds the LDS of a block");
     c->passes.clear();

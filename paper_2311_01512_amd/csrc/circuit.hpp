@@ -26,24 +26,49 @@ struct CircOp {
     }
 };
 
-constexpr int kTileDimMax = 14;
+// Tile steps.  A tile is the coset base ^ span(w_0..w_{d-1}) (reduced
+// echelon basis, coordinate k <-> w_k in ascending pivot order); element c
+// sits at base ^ (xor of w_k over the set bits k of c), and qubit b of
+// element c equals bit b of base ^ parity(c & m_b), m_b = sum_k (bit b of
+// w_k) << k.  Each thread of the block holds kRegs elements of the tile in
+// registers; which elements is the layout of a phase (RPhase), and every
+// operator of a phase only mixes elements held by one thread.
+constexpr int kRegBits = 3;
+constexpr int kRegs = 1 << kRegBits;
+constexpr int kTileDimMax = kRegBits + 10;   // 1024 threads per block
 
-// One operator of an LDS tile step, in the tile's coordinates.  The tile is
-// the coset base ^ span(w_0..w_{d-1}) (reduced echelon basis, coordinate k
-// <-> w_k in ascending pivot order); element c sits at base ^ (xor of w_k
-// over the set bits k of c), and qubit b of element c equals
-// bit b of base ^ parity(c & m_b), m_b = sum_k (bit b of w_k) << k.
-struct TOp {
-    int kind;            // 0: dense gate on unit-vector coordinates, 1: Pauli gadget
-    int nt, nc;          // dense: targets, controls
-    int pos[3];          // dense: target coordinates, ascending
-    int cq[4];           // dense: control qubits
-    uint32_t cm[4];      // dense: control coordinate masks m_c
-    uint32_t flip;       // gadget: coordinate flip of its X/Y mask (0: diagonal)
-    uint32_t yzm;        // gadget: xor of m_b over its Y/Z qubits
-    uint64_t yz;         // gadget: Y/Z qubit mask
-    int mat;             // dense: first entry of its matrix in the pass's table
-    double cs, cre, cim; // gadget: cos(theta) and i sin(theta) i^{#Y}
+// Thread t holds coordinates tau(t) ^ rho[u], u < kRegs: rho spans the
+// phase's register subspace (basis r_j with distinct highest bits, the
+// pivots), and tau deposits the bits of t, in order, at the coordinates
+// that are not pivots.
+struct RPhase {
+    uint32_t rho[kRegs];
+    uint32_t lo[kRegBits];          // (1 << pivot) - 1, pivots ascending
+    uint32_t pad_;
+    uint64_t yaddr[kRegs];          // index offset of rho[u] (xor of w_k)
+    uint64_t taddr[kTileDimMax];    // index offset of thread bit k
+    int first_op, num_ops;
+};
+
+// One operator of a phase, on register indices.
+//   code 1..7: dense gate whose targets are the register bits set in code
+//              (matrix bit i <-> i-th lowest of them); nc controls, control i
+//              is set where bit cq[i] of base ^ parity(tau & cm[i]) ^ bit i
+//              of qtab's nibble u is 1
+//   code 8:    diagonal Pauli gadget; code 9..15: gadget pairing register u
+//              with u ^ (code - 8).  Sign parity of element (t, u) is
+//              parity(base & yz) ^ parity(tau & yzm) ^ parity(u & gy).
+struct ROp {
+    int code;
+    int nc;
+    int cq[4];
+    uint32_t cm[4];
+    uint64_t qtab;
+    uint64_t yz;
+    uint32_t yzm, gy;
+    int mat;                        // first entry of its matrix in the table
+    int pad_;
+    double cs, cre, cim;            // gadget: cos(theta), i sin(theta) i^{#Y}
 };
 
 struct Pass {
@@ -61,7 +86,8 @@ struct Pass {
     int tile_d = 0;
     std::vector<uint64_t> basis;      // w_k by coordinate
     std::vector<int> pivots;          // pivot bit of w_k
-    std::vector<TOp> tops;
+    std::vector<RPhase> phases;
+    std::vector<ROp> rops;
     std::vector<cd> tmats;            // dense matrices of the step, concatenated
 };
 

@@ -1,15 +1,23 @@
-// LDS tile engine for recorded circuits.
+// Tile engine for recorded circuits.
 //
 // A step owns a subspace span(W) of the index space (GF(2) vectors, at most
 // T dimensions) that always contains the unit vectors of the lowest C
-// qubits, so each tile is read in runs of 2^C consecutive amplitudes (a full
-// 128-byte line).  A dense gate fits a step when the unit vectors of its
-// targets lie in span(W); a Pauli gadget fits when its X/Y flip mask does,
-// whatever its weight, since the gadget only pairs i with i ^ x.  Each tile
-// (coset base ^ span(W)) is gathered into LDS, every operator of the step is
-// applied there in order, and the tile is written back: one HBM pass for
-// the whole step.  Operators join a step only if they commute with every
-// operator they jump over (no shared qubit), so the circuit's order holds.
+// qubits, so each tile is read in runs of at least 2^C consecutive
+// amplitudes (a full 128-byte line).  A dense gate fits a step when the unit
+// vectors of its targets lie in span(W); a Pauli gadget fits when its X/Y
+// flip mask does, whatever its weight, since the gadget only pairs i with
+// i ^ x.  Each tile (coset base ^ span(W)) is read once from HBM into
+// registers, every operator of the step is applied, and the tile is written
+// back: one HBM pass for the whole step.  Operators join a step only if they
+// commute with every operator they jump over (no shared qubit), so the
+// circuit's order holds.
+//
+// Inside a step the operators run in phases.  In a phase each thread holds
+// kRegs tile elements whose coordinates form a coset of a kRegBits-dimensional
+// register subspace that contains the target unit vectors and flip vectors
+// of all the phase's operators, so every operator only mixes registers of
+// one thread: no LDS traffic and no barrier per operator.  Between phases
+// the tile moves through LDS once to the next layout.
 #include "circuit.hpp"
 
 #include <algorithm>
@@ -85,7 +93,48 @@ int tile_dim_limit(int precision)
     return d;
 }
 
-// Operators of a finished step in the step's coordinates.
+// ---- phases -----------------------------------------------------------------------------
+
+// Register basis of a phase in tile coordinates: the unit vectors of the
+// dense targets first, then the gadget flips reduced to new highest bits,
+// then (if pad) unit vectors of the highest free coordinates up to kRegBits.
+// Every vector has its own highest bit, so the set is independent and
+// completes to a basis with the unit vectors of the other coordinates.
+static int reg_basis(const std::vector<int> &units, const std::vector<uint32_t> &flips, int d, bool pad,
+                     std::vector<uint32_t> &r)
+{
+    r.clear();
+    uint32_t umask = 0;
+    for (int c : units)
+        if (!((umask >> c) & 1u)) {
+            umask |= 1u << c;
+            r.push_back(1u << c);
+        }
+    std::vector<uint32_t> g;
+    for (uint32_t f : flips) {
+        uint32_t x = f & ~umask;
+        while (x) {
+            const int hb = 31 - __builtin_clz(x);
+            auto it = std::find_if(g.begin(), g.end(), [&](uint32_t y) { return 31 - __builtin_clz(y) == hb; });
+            if (it == g.end()) break;
+            x ^= *it;
+        }
+        if (x) g.push_back(x);
+    }
+    r.insert(r.end(), g.begin(), g.end());
+    if (pad) {
+        uint32_t piv = 0;
+        for (uint32_t v : r) piv |= 1u << (31 - __builtin_clz(v));
+        for (int c = d - 1; c >= 0 && (int)r.size() < kRegBits; c--)
+            if (!((piv >> c) & 1u)) {
+                r.push_back(1u << c);
+                piv |= 1u << c;
+            }
+    }
+    return (int)r.size();
+}
+
+// Operators of a finished step in the step's coordinates, grouped in phases.
 static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircOp *> &members)
 {
     p.tile = true;
@@ -96,63 +145,154 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
         p.pivots.push_back(kv.first);
         p.basis.push_back(kv.second);
     }
-    p.tile_d = (int)p.basis.size();
+    const int d = (int)p.basis.size();
+    p.tile_d = d;
     auto coord_of_pivot = [&](int b) {
         return (int)(std::find(p.pivots.begin(), p.pivots.end(), b) - p.pivots.begin());
     };
     auto qubit_mask = [&](int b) {
         uint32_t m = 0;
-        for (int k = 0; k < p.tile_d; k++)
+        for (int k = 0; k < d; k++)
             if ((p.basis[k] >> b) & 1ULL) m |= 1u << k;
         return m;
     };
     auto flip_of = [&](uint64_t x) {
         uint32_t f = 0;
-        for (int k = 0; k < p.tile_d; k++)
+        for (int k = 0; k < d; k++)
             if ((x >> p.pivots[k]) & 1ULL) f |= 1u << k;
         return f;
     };
-    const cd eta[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
-    p.tops.clear();
-    p.tmats.clear();
-    for (const CircOp *op : members) {
-        TOp t{};
+    auto addr_of = [&](uint32_t c) {
+        uint64_t a = 0;
+        for (int k = 0; k < d; k++)
+            if ((c >> k) & 1u) a ^= p.basis[k];
+        return a;
+    };
+    // coordinate needs of each member: target unit vectors or the gadget flip
+    struct Need {
+        std::vector<int> units;
+        uint32_t flip;
+        uint64_t x, yz;
+        int ny;
+    };
+    std::vector<Need> needs(members.size());
+    for (size_t i = 0; i < members.size(); i++) {
+        const CircOp *op = members[i];
+        Need &n = needs[i];
+        n.flip = 0;
+        n.x = n.yz = 0;
+        n.ny = 0;
         if (op->gadget) {
-            t.kind = 1;
-            uint64_t x = 0, yz = 0;
-            int ny = 0;
             for (size_t k = 0; k < op->targs.size(); k++) {
                 const int c = op->paulis[k];
                 const uint64_t b = 1ULL << op->targs[k];
-                if (c == 1 || c == 2) x |= b;
-                if (c == 2 || c == 3) yz |= b;
-                if (c == 2) ny++;
+                if (c == 1 || c == 2) n.x |= b;
+                if (c == 2 || c == 3) n.yz |= b;
+                if (c == 2) n.ny++;
             }
-            t.flip = flip_of(x);
-            t.yz = yz;
-            uint32_t ym = 0;
-            for (int b = 0; b < 64; b++)
-                if ((yz >> b) & 1ULL) ym ^= qubit_mask(b);
-            t.yzm = ym;
-            const cd c = cd(0, std::sin(op->theta)) * eta[ny & 3];
-            t.cs = std::cos(op->theta);
-            t.cre = c.real();
-            t.cim = c.imag();
+            n.flip = flip_of(n.x);
         } else {
-            t.kind = 0;
-            std::vector<int> sorted;
-            std::vector<cd> Ms = permute_to_sorted(op->M, op->targs, sorted);
-            t.nt = (int)sorted.size();
-            for (int i = 0; i < t.nt; i++) t.pos[i] = coord_of_pivot(sorted[i]);
-            t.nc = (int)op->ctrls.size();
-            for (int i = 0; i < t.nc; i++) {
-                t.cq[i] = op->ctrls[i];
-                t.cm[i] = qubit_mask(op->ctrls[i]);
-            }
-            t.mat = (int)p.tmats.size();
-            p.tmats.insert(p.tmats.end(), Ms.begin(), Ms.end());
+            for (int t : op->targs) n.units.push_back(coord_of_pivot(t));
         }
-        p.tops.push_back(t);
+    }
+    const cd eta[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+    p.phases.clear();
+    p.rops.clear();
+    p.tmats.clear();
+    const int lb = d - kRegBits;
+    size_t i = 0;
+    while (i < members.size()) {
+        std::vector<int> units;
+        std::vector<uint32_t> flips, r;
+        size_t j = i;
+        for (; j < members.size(); j++) {
+            std::vector<int> u2 = units;
+            std::vector<uint32_t> f2 = flips;
+            u2.insert(u2.end(), needs[j].units.begin(), needs[j].units.end());
+            if (needs[j].flip) f2.push_back(needs[j].flip);
+            if (reg_basis(u2, f2, d, false, r) > kRegBits) break;
+            units.swap(u2);
+            flips.swap(f2);
+        }
+        reg_basis(units, flips, d, true, r);
+        RPhase ph{};
+        uint32_t piv = 0;
+        int pj[kRegBits];
+        for (int b = 0; b < kRegBits; b++) {
+            pj[b] = 31 - __builtin_clz(r[b]);
+            piv |= 1u << pj[b];
+        }
+        std::vector<int> sorted_piv(pj, pj + kRegBits);
+        std::sort(sorted_piv.begin(), sorted_piv.end());
+        for (int b = 0; b < kRegBits; b++) ph.lo[b] = (1u << sorted_piv[b]) - 1u;
+        for (int u = 0; u < kRegs; u++) {
+            uint32_t c = 0;
+            for (int b = 0; b < kRegBits; b++)
+                if ((u >> b) & 1) c ^= r[b];
+            ph.rho[u] = c;
+            ph.yaddr[u] = addr_of(c);
+        }
+        for (int k = 0, c = 0; k < lb; k++, c++) {
+            while ((piv >> c) & 1u) c++;
+            ph.taddr[k] = p.basis[c];
+        }
+        ph.first_op = (int)p.rops.size();
+        ph.num_ops = (int)(j - i);
+        auto reg_bit_of_unit = [&](int coord) {
+            for (int b = 0; b < kRegBits; b++)
+                if (r[b] == (1u << coord)) return b;
+            return -1;
+        };
+        for (size_t m = i; m < j; m++) {
+            const CircOp *op = members[m];
+            const Need &n = needs[m];
+            ROp ro{};
+            if (op->gadget) {
+                uint32_t f = n.flip, fu = 0;
+                while (f) {
+                    const int hb = 31 - __builtin_clz(f);
+                    int b = 0;
+                    while (b < kRegBits && pj[b] != hb) b++;
+                    f ^= r[b];
+                    fu |= 1u << b;
+                }
+                ro.code = 8 + (int)fu;
+                ro.yz = n.yz;
+                uint32_t ym = 0;
+                for (int b = 0; b < 64; b++)
+                    if ((n.yz >> b) & 1ULL) ym ^= qubit_mask(b);
+                ro.yzm = ym;
+                for (int b = 0; b < kRegBits; b++) ro.gy |= (uint32_t)(__builtin_popcount(r[b] & ym) & 1) << b;
+                const cd c = cd(0, std::sin(op->theta)) * eta[n.ny & 3];
+                ro.cs = std::cos(op->theta);
+                ro.cre = c.real();
+                ro.cim = c.imag();
+            } else {
+                std::vector<int> js, sorted;
+                uint32_t um = 0;
+                for (int c : n.units) {
+                    js.push_back(reg_bit_of_unit(c));
+                    um |= 1u << js.back();
+                }
+                std::vector<cd> Ms = permute_to_sorted(op->M, js, sorted);
+                ro.code = (int)um;
+                ro.nc = (int)op->ctrls.size();
+                for (int q = 0; q < ro.nc; q++) {
+                    ro.cq[q] = op->ctrls[q];
+                    ro.cm[q] = qubit_mask(op->ctrls[q]);
+                }
+                for (int u = 0; u < kRegs; u++) {
+                    uint64_t nib = 0;
+                    for (int q = 0; q < ro.nc; q++) nib |= (uint64_t)(__builtin_popcount(ph.rho[u] & ro.cm[q]) & 1) << q;
+                    ro.qtab |= nib << (4 * u);
+                }
+                ro.mat = (int)p.tmats.size();
+                p.tmats.insert(p.tmats.end(), Ms.begin(), Ms.end());
+            }
+            p.rops.push_back(ro);
+        }
+        p.phases.push_back(ph);
+        i = j;
     }
     p.members = (int)members.size();
 }
@@ -162,15 +302,16 @@ void plan_tiles(qs_circuit *c, int T, int precision)
     const int N = c->num_qubits;
     const int n_ops = (int)c->ops.size();
     const int C = std::min(N, precision == QS_C64 ? 4 : 3);
-    T = std::max(std::min(T, N), std::min(N, C + 3));
-    std::vector<char> placed(n_ops, 0);
+    T = std::min(T, N);
     const int lookahead = 512;
+    std::vector<char> placed(n_ops, 0);
     for (int i = 0; i < n_ops; i++) {
         if (placed[i]) continue;
         const CircOp &first = c->ops[i];
-        // controls beyond the 4 a tile operator carries, or gates of more
-        // than 3 targets, run as passes of their own
-        if (!absorbable(first) || first.ctrls.size() > 4) {
+        // registers need a tile of more than kRegBits dimensions; controls
+        // beyond the 4 a tile operator carries, or gates of more than 3
+        // targets, run as passes of their own
+        if (T <= kRegBits || !absorbable(first) || first.ctrls.size() > 4) {
             placed[i] = 1;
             c->passes.push_back(single_pass(first));
             continue;
@@ -197,245 +338,237 @@ void plan_tiles(qs_circuit *c, int T, int precision)
             }
             if (__builtin_popcountll(blocked) >= N) break;
         }
+        // fill the tile to T dimensions with the lowest free qubits: longer
+        // contiguous runs, fewer and larger tiles
+        for (int b = C; b < N && E.dim() < T; b++) E.add(1ULL << b);
         Pass p{};
         encode_step(p, E, members);
         c->passes.push_back(std::move(p));
     }
 }
 
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
 size_t tile_pass_bytes(const Pass &p, int precision)
 {
-    const size_t ops = ((p.tops.size() * sizeof(TOp)) + 255) & ~size_t(255);
-    return ops + p.tmats.size() * (precision == QS_C64 ? sizeof(float2) : sizeof(double2));
+    return align256(p.phases.size() * sizeof(RPhase)) + align256(p.rops.size() * sizeof(ROp)) +
+           p.tmats.size() * (precision == QS_C64 ? sizeof(float2) : sizeof(double2));
 }
 
 void pack_tile_pass(const Pass &p, int precision, void *out)
 {
     unsigned char *o = (unsigned char *)out;
-    std::memcpy(o, p.tops.data(), p.tops.size() * sizeof(TOp));
-    unsigned char *m = o + (((p.tops.size() * sizeof(TOp)) + 255) & ~size_t(255));
+    std::memcpy(o, p.phases.data(), p.phases.size() * sizeof(RPhase));
+    o += align256(p.phases.size() * sizeof(RPhase));
+    std::memcpy(o, p.rops.data(), p.rops.size() * sizeof(ROp));
+    o += align256(p.rops.size() * sizeof(ROp));
     for (size_t i = 0; i < p.tmats.size(); i++) {
         if (precision == QS_C64)
-            ((float2 *)m)[i] = make_float2((float)p.tmats[i].real(), (float)p.tmats[i].imag());
+            ((float2 *)o)[i] = make_float2((float)p.tmats[i].real(), (float)p.tmats[i].imag());
         else
-            ((double2 *)m)[i] = make_double2(p.tmats[i].real(), p.tmats[i].imag());
+            ((double2 *)o)[i] = make_double2(p.tmats[i].real(), p.tmats[i].imag());
     }
 }
 
 // ---- kernel -------------------------------------------------------------------------------
-//
-// EL = log2(tile entries per thread).  With EL fixed at compile time every
-// per-operator loop is unrolled: a thread first loads all of its pairs or
-// groups from LDS, then computes and stores them, so the LDS round trips of
-// one operator overlap instead of running one after another.
 
 struct TileArgs {
     int d;
-    int nops;
-    uint64_t w[kTileDimMax];
-    InsertPlan plan;     // zeros at the pivots: spreads the tile number
+    int nph;
+    InsertPlan plan;     // zeros at the tile's pivots: spreads the tile number
     uint64_t num_tiles;
 };
 
-template <int NT>
-__device__ __forceinline__ int spread_group(int g, const TOp &op)
+// i-th lowest set bit of mask receives bit i of l
+__host__ __device__ constexpr int deposit_bits(int l, int mask)
 {
-#pragma unroll
-    for (int i = 0; i < NT; i++) {
-        const int lo = (1 << op.pos[i]) - 1;
-        g = (g & lo) | ((g & ~lo) << 1);
-    }
-    return g;
-}
-
-template <int NT>
-__device__ __forceinline__ int local_member(int cb, int l, const TOp &op)
-{
-#pragma unroll
-    for (int i = 0; i < NT; i++)
-        if ((l >> i) & 1) cb |= 1 << op.pos[i];
-    return cb;
-}
-
-template <typename R, int NT, int EL>
-__device__ void tile_dense(C2<R> *v, int d, const TOp &op, uint64_t base, const C2<R> *__restrict__ mat)
-{
-    constexpr int D = 1 << NT;
-    constexpr int PER = (EL >= NT) ? (1 << (EL - NT)) : 1;   // groups per thread
-    const int groups = 1 << (d - NT);
-    C2<R> m[D * D];
-#pragma unroll
-    for (int k = 0; k < D * D; k++) m[k] = mat[k];
-    int cb[PER];
-    bool on[PER];
-    C2<R> x[PER][D];
-#pragma unroll
-    for (int u = 0; u < PER; u++) {
-        const int g = threadIdx.x + u * blockDim.x;
-        cb[u] = spread_group<NT>(g, op);
-        bool ok = g < groups;
-        for (int i = 0; i < op.nc; i++)
-            ok &= (((base >> op.cq[i]) & 1ULL) ^ (uint64_t)(__popc(cb[u] & op.cm[i]) & 1)) != 0;
-        on[u] = ok;
-        if (ok) {
-#pragma unroll
-            for (int l = 0; l < D; l++) x[u][l] = v[local_member<NT>(cb[u], l, op)];
+    int r = 0, k = 0;
+    for (int b = 0; b < kRegBits; b++)
+        if ((mask >> b) & 1) {
+            if ((l >> k) & 1) r |= 1 << b;
+            k++;
         }
+    return r;
+}
+
+__host__ __device__ constexpr int popcount_c(int m) { return m ? (m & 1) + popcount_c(m >> 1) : 0; }
+
+__device__ __forceinline__ uint32_t tau_of(uint32_t t, const RPhase &ph)
+{
+#pragma unroll
+    for (int b = 0; b < kRegBits; b++) {
+        const uint32_t lo = ph.lo[b];
+        t = (t & lo) | ((t & ~lo) << 1);
     }
+    return t;
+}
+
+__device__ __forceinline__ uint64_t thread_offset(uint32_t t, int lb, const RPhase &ph)
+{
+    uint64_t x = 0;
+    for (int k = 0; k < lb; k++)
+        if ((t >> k) & 1u) x ^= ph.taddr[k];
+    return x;
+}
+
+template <typename R, int UM>
+__device__ __forceinline__ void reg_dense(C2<R> (&x)[kRegs], const ROp &op, uint32_t tau, uint64_t base,
+                                          const C2<R> *__restrict__ m)
+{
+    constexpr int D = 1 << popcount_c(UM);
+    C2<R> y[kRegs];
 #pragma unroll
-    for (int u = 0; u < PER; u++) {
-        if (!on[u]) continue;
+    for (int j = 0; j < D; j++) {
+        C2<R> row[D];
 #pragma unroll
-        for (int j = 0; j < D; j++) {
+        for (int l = 0; l < D; l++) row[l] = m[j * D + l];
+#pragma unroll
+        for (int u0 = 0; u0 < kRegs; u0++) {
+            if (u0 & UM) continue;
             C2<R> acc = mk<R>(R(0), R(0));
 #pragma unroll
-            for (int l = 0; l < D; l++) cmac<R>(acc, m[j * D + l], x[u][l]);
-            v[local_member<NT>(cb[u], j, op)] = acc;
+            for (int l = 0; l < D; l++) cmac<R>(acc, row[l], x[u0 | deposit_bits(l, UM)]);
+            y[u0 | deposit_bits(j, UM)] = acc;
         }
+        // one matrix row in scalar registers at a time
+        asm volatile("" ::: "memory");
     }
-}
-
-template <typename R, int EL>
-__device__ void tile_gadget(C2<R> *v, int d, const TOp &op, uint64_t base)
-{
-    const int sb = __popcll(base & op.yz) & 1;
-    const R cs = (R)op.cs, cr = (R)op.cre, ci = (R)op.cim;
-    if (op.flip == 0) {
-        constexpr int PER = 1 << EL;
-        const int T = 1 << d;
-        C2<R> x[PER];
+    if (op.nc == 0) {
 #pragma unroll
-        for (int u = 0; u < PER; u++) {
-            const int c = threadIdx.x + u * blockDim.x;
-            if (c < T) x[u] = v[c];
-        }
-#pragma unroll
-        for (int u = 0; u < PER; u++) {
-            const int c = threadIdx.x + u * blockDim.x;
-            if (c < T) {
-                const R s = ((sb ^ __popc((unsigned)c & op.yzm)) & 1) ? R(-1) : R(1);
-                const C2<R> a = x[u];
-                v[c] = mk<R>(cs * a.x + s * (cr * a.x - ci * a.y), cs * a.y + s * (cr * a.y + ci * a.x));
-            }
-        }
+        for (int u = 0; u < kRegs; u++) x[u] = y[u];
         return;
     }
-    constexpr int PER = (EL >= 1) ? (1 << (EL - 1)) : 1;
-    const int np = 1 << (d - 1);
-    const int hb = 31 - __clz(op.flip);
-    const int lo = (1 << hb) - 1;
-    int c0[PER];
-    C2<R> a0[PER], a1[PER];
+    uint32_t tp = 0;
+    for (int i = 0; i < op.nc; i++)
+        tp |= (uint32_t)(((base >> op.cq[i]) ^ (uint64_t)__popc(tau & op.cm[i])) & 1ULL) << i;
+    const uint32_t full = (1u << op.nc) - 1u;
 #pragma unroll
-    for (int u = 0; u < PER; u++) {
-        const int p = threadIdx.x + u * blockDim.x;
-        c0[u] = (p & lo) | ((p & ~lo) << 1);
-        if (p < np) {
-            a0[u] = v[c0[u]];
-            a1[u] = v[c0[u] ^ (int)op.flip];
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < PER; u++) {
-        const int p = threadIdx.x + u * blockDim.x;
-        if (p >= np) continue;
-        const int c1 = c0[u] ^ (int)op.flip;
-        const R s0 = ((sb ^ __popc((unsigned)c0[u] & op.yzm)) & 1) ? R(-1) : R(1);
-        const R s1 = ((sb ^ __popc((unsigned)c1 & op.yzm)) & 1) ? R(-1) : R(1);
-        const C2<R> x0 = a0[u], x1 = a1[u];
-        v[c0[u]] = mk<R>(cs * x0.x + s1 * (cr * x1.x - ci * x1.y), cs * x0.y + s1 * (cr * x1.y + ci * x1.x));
-        v[c1] = mk<R>(cs * x1.x + s0 * (cr * x0.x - ci * x0.y), cs * x1.y + s0 * (cr * x0.y + ci * x0.x));
+    for (int u = 0; u < kRegs; u++) {
+        const uint32_t q = (uint32_t)(op.qtab >> (4 * u)) & 15u;
+        if ((tp ^ q) == full) x[u] = y[u];
     }
 }
 
-template <typename R, int EL>
-__global__ __launch_bounds__(1024) void k_tile_step(C2<R> *__restrict__ a, TileArgs ta, const TOp *__restrict__ tops,
-                                                     const C2<R> *__restrict__ mats)
+template <typename R, int FU>
+__device__ __forceinline__ void reg_gadget(C2<R> (&x)[kRegs], const ROp &op, uint32_t tau, uint64_t base)
 {
-    extern __shared__ unsigned char lds_raw[];
-    C2<R> *v = reinterpret_cast<C2<R> *>(lds_raw);
-    constexpr int PER = 1 << EL;
-    const int T = 1 << ta.d;
-    const int lb = 31 - __clz(blockDim.x);   // block size is a power of two
-    // coordinates c = threadIdx.x + blockDim.x u: the address is linear in c
-    uint64_t xt = 0;
-    for (int k = 0; k < lb && k < ta.d; k++)
-        if ((threadIdx.x >> k) & 1) xt ^= ta.w[k];
-    uint64_t xu[PER];
+    const uint32_t st = (uint32_t)(__popcll(base & op.yz) + __popc(tau & op.yzm)) & 1u;
+    const R sg = st ? R(-1) : R(1);
+    const R cs = (R)op.cs, cr = (R)op.cre, ci = (R)op.cim;
+    if constexpr (FU == 0) {
 #pragma unroll
-    for (int u = 0; u < PER; u++) {
-        uint64_t x = xt;
-        for (int k = lb; k < ta.d; k++)
-            if ((u >> (k - lb)) & 1) x ^= ta.w[k];
-        xu[u] = x;
-    }
-    for (uint64_t tile = blockIdx.x; tile < ta.num_tiles; tile += gridDim.x) {
-        const uint64_t base = insert_zeros(tile, ta.plan);
-#pragma unroll
-        for (int u = 0; u < PER; u++)
-            if ((int)threadIdx.x + (u << lb) < T) v[threadIdx.x + (u << lb)] = a[base ^ xu[u]];
-        __syncthreads();
-        for (int o = 0; o < ta.nops; o++) {
-            const TOp &op = tops[o];
-            if (op.kind == 1) {
-                tile_gadget<R, EL>(v, ta.d, op, base);
-            } else {
-                const C2<R> *m = mats + op.mat;
-                if (op.nt == 1) tile_dense<R, 1, EL>(v, ta.d, op, base, m);
-                else if (op.nt == 2) tile_dense<R, 2, EL>(v, ta.d, op, base, m);
-                else tile_dense<R, 3, EL>(v, ta.d, op, base, m);
-            }
-            __syncthreads();
+        for (int u = 0; u < kRegs; u++) {
+            const R s = (__popc((uint32_t)u & op.gy) & 1) ? -sg : sg;
+            const R kr = cs + s * cr, ki = s * ci;
+            const C2<R> a = x[u];
+            x[u] = mk<R>(kr * a.x - ki * a.y, kr * a.y + ki * a.x);
         }
+    } else {
+        constexpr int HB = 31 - __builtin_clz((unsigned)FU);
 #pragma unroll
-        for (int u = 0; u < PER; u++)
-            if ((int)threadIdx.x + (u << lb) < T) a[base ^ xu[u]] = v[threadIdx.x + (u << lb)];
-        __syncthreads();
+        for (int u0 = 0; u0 < kRegs; u0++) {
+            if ((u0 >> HB) & 1) continue;
+            const int u1 = u0 ^ FU;
+            const R s0 = (__popc((uint32_t)u0 & op.gy) & 1) ? -sg : sg;
+            const R s1 = (__popc((uint32_t)u1 & op.gy) & 1) ? -sg : sg;
+            const C2<R> x0 = x[u0], x1 = x[u1];
+            x[u0] = mk<R>(cs * x0.x + s1 * (cr * x1.x - ci * x1.y), cs * x0.y + s1 * (cr * x1.y + ci * x1.x));
+            x[u1] = mk<R>(cs * x1.x + s0 * (cr * x0.x - ci * x0.y), cs * x1.y + s0 * (cr * x0.y + ci * x0.x));
+        }
     }
 }
 
 template <typename R>
-static int launch_tile_r(qs_qureg *q, int el, unsigned grid, unsigned block, size_t lds, const TileArgs &ta,
-                         const TOp *tops, const C2<R> *mats)
+__device__ __forceinline__ void apply_reg_op(C2<R> (&x)[kRegs], const ROp &op, uint32_t tau, uint64_t base,
+                                             const C2<R> *__restrict__ mats)
 {
-    C2<R> *amps = (C2<R> *)q->amps;
-    switch (el) {
-    case 0: hipLaunchKernelGGL((k_tile_step<R, 0>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
-    case 1: hipLaunchKernelGGL((k_tile_step<R, 1>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
-    case 2: hipLaunchKernelGGL((k_tile_step<R, 2>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
-    case 3: hipLaunchKernelGGL((k_tile_step<R, 3>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
-    case 4: hipLaunchKernelGGL((k_tile_step<R, 4>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
-    case 5: hipLaunchKernelGGL((k_tile_step<R, 5>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
-    default: hipLaunchKernelGGL((k_tile_step<R, 6>), dim3(grid), dim3(block), lds, q->stream, amps, ta, tops, mats); break;
+    const C2<R> *m = mats + op.mat;
+    switch (op.code) {
+    case 1: reg_dense<R, 1>(x, op, tau, base, m); break;
+    case 2: reg_dense<R, 2>(x, op, tau, base, m); break;
+    case 3: reg_dense<R, 3>(x, op, tau, base, m); break;
+    case 4: reg_dense<R, 4>(x, op, tau, base, m); break;
+    case 5: reg_dense<R, 5>(x, op, tau, base, m); break;
+    case 6: reg_dense<R, 6>(x, op, tau, base, m); break;
+    case 7: reg_dense<R, 7>(x, op, tau, base, m); break;
+    case 8: reg_gadget<R, 0>(x, op, tau, base); break;
+    case 9: reg_gadget<R, 1>(x, op, tau, base); break;
+    case 10: reg_gadget<R, 2>(x, op, tau, base); break;
+    case 11: reg_gadget<R, 3>(x, op, tau, base); break;
+    case 12: reg_gadget<R, 4>(x, op, tau, base); break;
+    case 13: reg_gadget<R, 5>(x, op, tau, base); break;
+    case 14: reg_gadget<R, 6>(x, op, tau, base); break;
+    default: reg_gadget<R, 7>(x, op, tau, base); break;
     }
-    QS_LAUNCH_CHECK();
-    return QS_OK;
+}
+
+// One block per tile, 2^(d - kRegBits) threads; the tile is read from HBM
+// straight into the first phase's layout and written from the last one's.
+template <typename R>
+__global__ __launch_bounds__(1024) void k_tile_step(C2<R> *__restrict__ a, TileArgs ta, const RPhase *__restrict__ ph,
+                                                     const ROp *__restrict__ ops, const C2<R> *__restrict__ mats)
+{
+    extern __shared__ unsigned char lds_raw[];
+    C2<R> *v = reinterpret_cast<C2<R> *>(lds_raw);
+    const uint32_t t = threadIdx.x;
+    const int lb = ta.d - kRegBits;
+    const RPhase &first = ph[0];
+    const RPhase &last = ph[ta.nph - 1];
+    const uint64_t xg = thread_offset(t, lb, first);
+    const uint64_t xs = thread_offset(t, lb, last);
+    for (uint64_t tile = blockIdx.x; tile < ta.num_tiles; tile += gridDim.x) {
+        const uint64_t base = insert_zeros(tile, ta.plan);
+        C2<R> x[kRegs];
+#pragma unroll
+        for (int u = 0; u < kRegs; u++) x[u] = a[base ^ xg ^ first.yaddr[u]];
+        uint32_t tau = tau_of(t, first);
+        for (int p = 0; p < ta.nph; p++) {
+            const RPhase &P = ph[p];
+            if (p > 0) {
+                const RPhase &Q = ph[p - 1];
+                const uint32_t tn = tau_of(t, P);
+                __syncthreads();   // earlier reads of the LDS tile are done
+#pragma unroll
+                for (int u = 0; u < kRegs; u++) v[tau ^ Q.rho[u]] = x[u];
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < kRegs; u++) x[u] = v[tn ^ P.rho[u]];
+                tau = tn;
+            }
+            const int end = P.first_op + P.num_ops;
+            for (int o = P.first_op; o < end; o++) apply_reg_op<R>(x, ops[o], tau, base, mats);
+        }
+#pragma unroll
+        for (int u = 0; u < kRegs; u++) a[base ^ xs ^ last.yaddr[u]] = x[u];
+    }
 }
 
 int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev)
 {
     if (!dev) return fail(QS_E_PRECOND, "tile pass without device tables");
+    if (p.phases.empty()) return QS_OK;
+    if (p.tile_d <= kRegBits || p.tile_d > kTileDimMax) return fail(QS_E_ARG, "tile dimension out of range");
     TileArgs ta{};
     ta.d = p.tile_d;
-    ta.nops = (int)p.tops.size();
-    for (int k = 0; k < p.tile_d; k++) ta.w[k] = p.basis[k];
+    ta.nph = (int)p.phases.size();
     ta.plan = make_insert_plan(p.pivots);
     ta.num_tiles = 1ULL << (q->index_bits - p.tile_d);
     const unsigned char *d = (const unsigned char *)dev;
-    const unsigned char *mats = d + (((p.tops.size() * sizeof(TOp)) + 255) & ~size_t(255));
+    const RPhase *ph = (const RPhase *)d;
+    const ROp *ops = (const ROp *)(d + align256(p.phases.size() * sizeof(RPhase)));
+    const unsigned char *mats = (const unsigned char *)ops + align256(p.rops.size() * sizeof(ROp));
     const size_t ab = q->precision == QS_C64 ? sizeof(float2) : sizeof(double2);
     const size_t lds = ((size_t)1 << p.tile_d) * ab;
-    // threads per block: 8 tile entries per thread (measured best), between
-    // 64 and 1024 threads, unless QS_TILE_BLOCK overrides it
-    int lb = std::min(10, std::max(6, p.tile_d - 3));
-    if (const int forced = tile_block_size()) lb = 31 - __builtin_clz((unsigned)forced);
-    while (p.tile_d - lb > 4 && lb < 10) lb++;
-    const unsigned block = 1u << lb;
-    const int el = std::max(0, p.tile_d - lb);
+    const unsigned block = 1u << (p.tile_d - kRegBits);
     const unsigned grid = grid_for(ta.num_tiles, 1, 0xFFFFFFFFull / block);
     if (q->precision == QS_C64)
-        return launch_tile_r<float>(q, el, grid, block, lds, ta, (const TOp *)d, (const float2 *)mats);
-    return launch_tile_r<double>(q, el, grid, block, lds, ta, (const TOp *)d, (const double2 *)mats);
+        hipLaunchKernelGGL(k_tile_step<float>, dim3(grid), dim3(block), lds, q->stream, (float2 *)q->amps, ta, ph, ops,
+                           (const float2 *)mats);
+    else
+        hipLaunchKernelGGL(k_tile_step<double>, dim3(grid), dim3(block), lds, q->stream, (double2 *)q->amps, ta, ph,
+                           ops, (const double2 *)mats);
+    QS_LAUNCH_CHECK();
+    return QS_OK;
 }
 
 }  // namespace qs
