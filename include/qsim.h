@@ -239,10 +239,12 @@ int qs_apply_circuit_passes(qs_qureg *q, qs_circuit *c, int first, int count);
 
 /* Describes pass `index` of the compiled circuit: kernel = 0 Pauli-gadget
  * pairs, 1 phase gadget (diagonal), 2 dense gate on vector FMAs, 3 dense
- * gate on FP32 MFMA; num_targs / num_ctrls of a dense pass (gadget: its
- * Pauli count, 0); members = recorded ops merged into the pass. */
+ * gate on FP32 MFMA, 4 tile step; num_targs / num_ctrls of a dense pass
+ * (gadget: its Pauli count, 0; tile step: its dimension, 0); members =
+ * recorded ops merged into the pass; phases = register layouts a tile step
+ * moves through (1 for other passes).  Any out pointer may be NULL. */
 int qs_circuit_pass_info(const qs_circuit *c, int index, int *kernel, int *num_targs, int *num_ctrls,
-                         int *members);
+                         int *members, int *phases);
 
 /*
  * Autotuner of the fusion width: compiles the circuit for each candidate k

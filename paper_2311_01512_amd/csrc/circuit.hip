@@ -348,7 +348,8 @@ int circuit_num_qubits(const qs_circuit *c) { return c->num_qubits; }
 
 extern "C" {
 
-int qs_circuit_pass_info(const qs_circuit *c, int index, int *kernel, int *num_targs, int *num_ctrls, int *members)
+int qs_circuit_pass_info(const qs_circuit *c, int index, int *kernel, int *num_targs, int *num_ctrls, int *members,
+                         int *phases)
 {
     if (!c) return fail(QS_E_ARG, "null circuit");
     if (!c->compiled) return fail(QS_E_PRECOND, "circuit is not compiled");
@@ -379,6 +380,7 @@ int qs_circuit_pass_info(const qs_circuit *c, int index, int *kernel, int *num_t
     if (num_targs) *num_targs = nt;
     if (num_ctrls) *num_ctrls = nc;
     if (members) *members = p.members;
+    if (phases) *phases = p.tile ? (int)p.phases.size() : 1;
     return QS_OK;
 }
 

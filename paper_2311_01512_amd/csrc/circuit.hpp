@@ -52,12 +52,13 @@ struct RPhase {
 
 // One operator of a phase, on register indices.
 //   code 1..7: dense gate whose targets are the register bits set in code
-//              (matrix bit i <-> i-th lowest of them); nc controls, control i
-//              is set where bit cq[i] of base ^ parity(tau & cm[i]) ^ bit i
-//              of qtab's nibble u is 1
+//              (matrix bit i <-> i-th lowest of them); 17..23: the same with
+//              nc controls, control i set where bit cq[i] of base ^
+//              parity(tau & cm[i]) ^ bit i of qtab's nibble u is 1
 //   code 8:    diagonal Pauli gadget; code 9..15: gadget pairing register u
 //              with u ^ (code - 8).  Sign parity of element (t, u) is
-//              parity(base & yz) ^ parity(tau & yzm) ^ parity(u & gy).
+//              parity(base & yz) ^ parity(tau & yzm) ^ parity(u & gy); the
+//              partner's sign is folded into (pre, pim).
 struct ROp {
     int code;
     int nc;
@@ -69,6 +70,7 @@ struct ROp {
     int mat;                        // first entry of its matrix in the table
     int pad_;
     double cs, cre, cim;            // gadget: cos(theta), i sin(theta) i^{#Y}
+    double pre, pim;                // (cre, cim) times (-1)^parity(x & yz)
 };
 
 struct Pass {

@@ -22,6 +22,8 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
+#include <tuple>
 
 namespace qs {
 
@@ -200,20 +202,37 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
     p.rops.clear();
     p.tmats.clear();
     const int lb = d - kRegBits;
-    size_t i = 0;
-    while (i < members.size()) {
+    // A phase takes, in order, every remaining member that fits its register
+    // space and shares no qubit with a remaining member it jumps over.
+    std::vector<size_t> remaining(members.size());
+    for (size_t m = 0; m < members.size(); m++) remaining[m] = m;
+    while (!remaining.empty()) {
         std::vector<int> units;
         std::vector<uint32_t> flips, r;
-        size_t j = i;
-        for (; j < members.size(); j++) {
-            std::vector<int> u2 = units;
-            std::vector<uint32_t> f2 = flips;
-            u2.insert(u2.end(), needs[j].units.begin(), needs[j].units.end());
-            if (needs[j].flip) f2.push_back(needs[j].flip);
-            if (reg_basis(u2, f2, d, false, r) > kRegBits) break;
-            units.swap(u2);
-            flips.swap(f2);
+        std::vector<size_t> chosen, rest;
+        uint64_t blocked = 0;
+        for (size_t m : remaining) {
+            const uint64_t s = support_mask(*members[m]);
+            bool take = false;
+            if (!(s & blocked)) {
+                std::vector<int> u2 = units;
+                std::vector<uint32_t> f2 = flips;
+                u2.insert(u2.end(), needs[m].units.begin(), needs[m].units.end());
+                if (needs[m].flip) f2.push_back(needs[m].flip);
+                if (reg_basis(u2, f2, d, false, r) <= kRegBits) {
+                    units.swap(u2);
+                    flips.swap(f2);
+                    take = true;
+                }
+            }
+            if (take) {
+                chosen.push_back(m);
+            } else {
+                blocked |= s;
+                rest.push_back(m);
+            }
         }
+        remaining.swap(rest);
         reg_basis(units, flips, d, true, r);
         RPhase ph{};
         uint32_t piv = 0;
@@ -237,13 +256,13 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
             ph.taddr[k] = p.basis[c];
         }
         ph.first_op = (int)p.rops.size();
-        ph.num_ops = (int)(j - i);
+        ph.num_ops = (int)chosen.size();
         auto reg_bit_of_unit = [&](int coord) {
             for (int b = 0; b < kRegBits; b++)
                 if (r[b] == (1u << coord)) return b;
             return -1;
         };
-        for (size_t m = i; m < j; m++) {
+        for (size_t m : chosen) {
             const CircOp *op = members[m];
             const Need &n = needs[m];
             ROp ro{};
@@ -264,9 +283,12 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
                 ro.yzm = ym;
                 for (int b = 0; b < kRegBits; b++) ro.gy |= (uint32_t)(__builtin_popcount(r[b] & ym) & 1) << b;
                 const cd c = cd(0, std::sin(op->theta)) * eta[n.ny & 3];
+                const double partner = (__builtin_popcountll(n.x & n.yz) & 1) ? -1.0 : 1.0;
                 ro.cs = std::cos(op->theta);
                 ro.cre = c.real();
                 ro.cim = c.imag();
+                ro.pre = partner * c.real();
+                ro.pim = partner * c.imag();
             } else {
                 std::vector<int> js, sorted;
                 uint32_t um = 0;
@@ -275,8 +297,8 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
                     um |= 1u << js.back();
                 }
                 std::vector<cd> Ms = permute_to_sorted(op->M, js, sorted);
-                ro.code = (int)um;
                 ro.nc = (int)op->ctrls.size();
+                ro.code = (int)um + (ro.nc > 0 ? 16 : 0);
                 for (int q = 0; q < ro.nc; q++) {
                     ro.cq[q] = op->ctrls[q];
                     ro.cm[q] = qubit_mask(op->ctrls[q]);
@@ -292,7 +314,6 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
             p.rops.push_back(ro);
         }
         p.phases.push_back(ph);
-        i = j;
     }
     p.members = (int)members.size();
 }
@@ -411,69 +432,73 @@ __device__ __forceinline__ uint64_t thread_offset(uint32_t t, int lb, const RPha
     return x;
 }
 
-template <typename R, int UM>
+template <typename R, int UM, bool CTRL>
 __device__ __forceinline__ void reg_dense(C2<R> (&x)[kRegs], const ROp &op, uint32_t tau, uint64_t base,
                                           const C2<R> *__restrict__ m)
 {
     constexpr int D = 1 << popcount_c(UM);
-    C2<R> y[kRegs];
+    uint32_t tp = 0, full = 0;
+    if constexpr (CTRL) {
+        for (int i = 0; i < op.nc; i++)
+            tp |= (uint32_t)(((base >> op.cq[i]) ^ (uint64_t)__popc(tau & op.cm[i])) & 1ULL) << i;
+        full = (1u << op.nc) - 1u;
+    }
 #pragma unroll
-    for (int j = 0; j < D; j++) {
-        C2<R> row[D];
+    for (int u0 = 0; u0 < kRegs; u0++) {
+        if (u0 & UM) continue;
+        // groups whose controls are not all set are left alone; where that
+        // holds for a whole wave (controls outside the lane coordinates, the
+        // common case) the arithmetic is skipped
+        if constexpr (CTRL)
+            if ((tp ^ ((uint32_t)(op.qtab >> (4 * u0)) & 15u)) != full) continue;
+        C2<R> in[D];
 #pragma unroll
-        for (int l = 0; l < D; l++) row[l] = m[j * D + l];
+        for (int l = 0; l < D; l++) in[l] = x[u0 | deposit_bits(l, UM)];
 #pragma unroll
-        for (int u0 = 0; u0 < kRegs; u0++) {
-            if (u0 & UM) continue;
+        for (int j = 0; j < D; j++) {
             C2<R> acc = mk<R>(R(0), R(0));
 #pragma unroll
-            for (int l = 0; l < D; l++) cmac<R>(acc, row[l], x[u0 | deposit_bits(l, UM)]);
-            y[u0 | deposit_bits(j, UM)] = acc;
+            for (int l = 0; l < D; l++) cmac<R>(acc, m[j * D + l], in[l]);
+            x[u0 | deposit_bits(j, UM)] = acc;
+            // an 8x8 matrix row by row, not all 64 entries in scalar registers
+            if constexpr (D == 8) asm volatile("" ::: "memory");
         }
-        // one matrix row in scalar registers at a time
-        asm volatile("" ::: "memory");
-    }
-    if (op.nc == 0) {
-#pragma unroll
-        for (int u = 0; u < kRegs; u++) x[u] = y[u];
-        return;
-    }
-    uint32_t tp = 0;
-    for (int i = 0; i < op.nc; i++)
-        tp |= (uint32_t)(((base >> op.cq[i]) ^ (uint64_t)__popc(tau & op.cm[i])) & 1ULL) << i;
-    const uint32_t full = (1u << op.nc) - 1u;
-#pragma unroll
-    for (int u = 0; u < kRegs; u++) {
-        const uint32_t q = (uint32_t)(op.qtab >> (4 * u)) & 15u;
-        if ((tp ^ q) == full) x[u] = y[u];
     }
 }
 
+// Element (t, u) has sign parity st ^ parity(u & gy); the pair partner's
+// parity differs by parity(x & yz), folded into cre/cim on the host as a
+// second constant (ROp::pre/pim) so both outputs use the parity of u0.
 template <typename R, int FU>
 __device__ __forceinline__ void reg_gadget(C2<R> (&x)[kRegs], const ROp &op, uint32_t tau, uint64_t base)
 {
     const uint32_t st = (uint32_t)(__popcll(base & op.yz) + __popc(tau & op.yzm)) & 1u;
     const R sg = st ? R(-1) : R(1);
-    const R cs = (R)op.cs, cr = (R)op.cre, ci = (R)op.cim;
+    const R cs = (R)op.cs;
+    const R kr = sg * (R)op.cre, ki = sg * (R)op.cim;   // this thread's sign times i sin(theta) i^{#Y}
     if constexpr (FU == 0) {
+        const R pr = cs + kr, mr = cs - kr, mi = -ki;
 #pragma unroll
         for (int u = 0; u < kRegs; u++) {
-            const R s = (__popc((uint32_t)u & op.gy) & 1) ? -sg : sg;
-            const R kr = cs + s * cr, ki = s * ci;
+            const bool neg = __popc((uint32_t)u & op.gy) & 1;
+            const R ar = neg ? mr : pr, ai = neg ? mi : ki;
             const C2<R> a = x[u];
-            x[u] = mk<R>(kr * a.x - ki * a.y, kr * a.y + ki * a.x);
+            x[u] = mk<R>(ar * a.x - ai * a.y, ar * a.y + ai * a.x);
         }
     } else {
         constexpr int HB = 31 - __builtin_clz((unsigned)FU);
+        const R qr = sg * (R)op.pre, qi = sg * (R)op.pim;   // the same for the partner's sign
 #pragma unroll
         for (int u0 = 0; u0 < kRegs; u0++) {
             if ((u0 >> HB) & 1) continue;
             const int u1 = u0 ^ FU;
-            const R s0 = (__popc((uint32_t)u0 & op.gy) & 1) ? -sg : sg;
-            const R s1 = (__popc((uint32_t)u1 & op.gy) & 1) ? -sg : sg;
+            const R pm = (__popc((uint32_t)u0 & op.gy) & 1) ? R(-1) : R(1);   // uniform
             const C2<R> x0 = x[u0], x1 = x[u1];
-            x[u0] = mk<R>(cs * x0.x + s1 * (cr * x1.x - ci * x1.y), cs * x0.y + s1 * (cr * x1.y + ci * x1.x));
-            x[u1] = mk<R>(cs * x1.x + s0 * (cr * x0.x - ci * x0.y), cs * x1.y + s0 * (cr * x0.y + ci * x0.x));
+            // x0' = cs x0 + s(u1) c x1,  x1' = cs x1 + s(u0) c x0
+            const C2<R> t1 = mk<R>(qr * x1.x - qi * x1.y, qr * x1.y + qi * x1.x);
+            const C2<R> t0 = mk<R>(kr * x0.x - ki * x0.y, kr * x0.y + ki * x0.x);
+            x[u0] = mk<R>(fma(pm, t1.x, cs * x0.x), fma(pm, t1.y, cs * x0.y));
+            x[u1] = mk<R>(fma(pm, t0.x, cs * x1.x), fma(pm, t0.y, cs * x1.y));
         }
     }
 }
@@ -484,13 +509,13 @@ __device__ __forceinline__ void apply_reg_op(C2<R> (&x)[kRegs], const ROp &op, u
 {
     const C2<R> *m = mats + op.mat;
     switch (op.code) {
-    case 1: reg_dense<R, 1>(x, op, tau, base, m); break;
-    case 2: reg_dense<R, 2>(x, op, tau, base, m); break;
-    case 3: reg_dense<R, 3>(x, op, tau, base, m); break;
-    case 4: reg_dense<R, 4>(x, op, tau, base, m); break;
-    case 5: reg_dense<R, 5>(x, op, tau, base, m); break;
-    case 6: reg_dense<R, 6>(x, op, tau, base, m); break;
-    case 7: reg_dense<R, 7>(x, op, tau, base, m); break;
+    case 1: reg_dense<R, 1, false>(x, op, tau, base, m); break;
+    case 2: reg_dense<R, 2, false>(x, op, tau, base, m); break;
+    case 3: reg_dense<R, 3, false>(x, op, tau, base, m); break;
+    case 4: reg_dense<R, 4, false>(x, op, tau, base, m); break;
+    case 5: reg_dense<R, 5, false>(x, op, tau, base, m); break;
+    case 6: reg_dense<R, 6, false>(x, op, tau, base, m); break;
+    case 7: reg_dense<R, 7, false>(x, op, tau, base, m); break;
     case 8: reg_gadget<R, 0>(x, op, tau, base); break;
     case 9: reg_gadget<R, 1>(x, op, tau, base); break;
     case 10: reg_gadget<R, 2>(x, op, tau, base); break;
@@ -498,41 +523,67 @@ __device__ __forceinline__ void apply_reg_op(C2<R> (&x)[kRegs], const ROp &op, u
     case 12: reg_gadget<R, 4>(x, op, tau, base); break;
     case 13: reg_gadget<R, 5>(x, op, tau, base); break;
     case 14: reg_gadget<R, 6>(x, op, tau, base); break;
-    default: reg_gadget<R, 7>(x, op, tau, base); break;
+    case 15: reg_gadget<R, 7>(x, op, tau, base); break;
+    case 17: reg_dense<R, 1, true>(x, op, tau, base, m); break;
+    case 18: reg_dense<R, 2, true>(x, op, tau, base, m); break;
+    case 19: reg_dense<R, 3, true>(x, op, tau, base, m); break;
+    case 20: reg_dense<R, 4, true>(x, op, tau, base, m); break;
+    case 21: reg_dense<R, 5, true>(x, op, tau, base, m); break;
+    case 22: reg_dense<R, 6, true>(x, op, tau, base, m); break;
+    default: reg_dense<R, 7, true>(x, op, tau, base, m); break;
     }
 }
 
-// One block per tile, 2^(d - kRegBits) threads; the tile is read from HBM
-// straight into the first phase's layout and written from the last one's.
+// Persistent blocks of 2^(d - kRegBits) threads, each walking tiles
+// blockIdx.x + k gridDim.x.  A tile is read from HBM straight into the first
+// phase's layout and written from the last one's; the next tile's loads are
+// issued before the current tile's operators run, so they are in flight
+// during the arithmetic (barriers here wait for LDS only).  Tiles are
+// disjoint, so the early read sees no write of this launch.
 template <typename R>
 __global__ __launch_bounds__(1024) void k_tile_step(C2<R> *__restrict__ a, TileArgs ta, const RPhase *__restrict__ ph,
                                                      const ROp *__restrict__ ops, const C2<R> *__restrict__ mats)
 {
     extern __shared__ unsigned char lds_raw[];
-    C2<R> *v = reinterpret_cast<C2<R> *>(lds_raw);
     const uint32_t t = threadIdx.x;
     const int lb = ta.d - kRegBits;
     const RPhase &first = ph[0];
     const RPhase &last = ph[ta.nph - 1];
     const uint64_t xg = thread_offset(t, lb, first);
     const uint64_t xs = thread_offset(t, lb, last);
-    for (uint64_t tile = blockIdx.x; tile < ta.num_tiles; tile += gridDim.x) {
+    uint64_t tile = blockIdx.x;
+    if (tile >= ta.num_tiles) return;
+    C2<R> nx[kRegs];
+    {
+        const uint64_t b0 = insert_zeros(tile, ta.plan);
+#pragma unroll
+        for (int u = 0; u < kRegs; u++) nx[u] = a[b0 ^ xg ^ first.yaddr[u]];
+    }
+    for (; tile < ta.num_tiles; tile += gridDim.x) {
         const uint64_t base = insert_zeros(tile, ta.plan);
         C2<R> x[kRegs];
 #pragma unroll
-        for (int u = 0; u < kRegs; u++) x[u] = a[base ^ xg ^ first.yaddr[u]];
+        for (int u = 0; u < kRegs; u++) x[u] = nx[u];
+        const uint64_t next = tile + gridDim.x;
+        if (next < ta.num_tiles) {
+            const uint64_t nb = insert_zeros(next, ta.plan);
+#pragma unroll
+            for (int u = 0; u < kRegs; u++) nx[u] = a[nb ^ xg ^ first.yaddr[u]];
+        }
         uint32_t tau = tau_of(t, first);
         for (int p = 0; p < ta.nph; p++) {
             const RPhase &P = ph[p];
             if (p > 0) {
                 const RPhase &Q = ph[p - 1];
                 const uint32_t tn = tau_of(t, P);
+                constexpr int sh = sizeof(C2<R>) == 8 ? 3 : 4;
+                const uint32_t ob = tau << sh, nb = tn << sh;
                 __syncthreads();   // earlier reads of the LDS tile are done
 #pragma unroll
-                for (int u = 0; u < kRegs; u++) v[tau ^ Q.rho[u]] = x[u];
+                for (int u = 0; u < kRegs; u++) *(C2<R> *)(lds_raw + (ob ^ (Q.rho[u] << sh))) = x[u];
                 __syncthreads();
 #pragma unroll
-                for (int u = 0; u < kRegs; u++) x[u] = v[tn ^ P.rho[u]];
+                for (int u = 0; u < kRegs; u++) x[u] = *(const C2<R> *)(lds_raw + (nb ^ (P.rho[u] << sh)));
                 tau = tn;
             }
             const int end = P.first_op + P.num_ops;
@@ -560,7 +611,24 @@ int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev)
     const size_t ab = q->precision == QS_C64 ? sizeof(float2) : sizeof(double2);
     const size_t lds = ((size_t)1 << p.tile_d) * ab;
     const unsigned block = 1u << (p.tile_d - kRegBits);
-    const unsigned grid = grid_for(ta.num_tiles, 1, 0xFFFFFFFFull / block);
+    // as many blocks as stay resident, so each walks many tiles
+    static std::map<std::tuple<int, int, int>, int> resident;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(q->device, q->precision, p.tile_d);
+    auto it = resident.find(key);
+    if (it == resident.end()) {
+        int per_cu = 0, cus = 0;
+        const hipError_t e1 =
+            q->precision == QS_C64
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_step<float>, (int)block, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_step<double>, (int)block, lds);
+        const hipError_t e2 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, q->device);
+        if (e1 != hipSuccess || e2 != hipSuccess || per_cu < 1 || cus < 1)
+            return fail(QS_E_HIP, "occupancy query for the tile kernel failed");
+        it = resident.emplace(key, per_cu * cus).first;
+    }
+    const unsigned grid = grid_for(ta.num_tiles, 1, (uint64_t)it->second);
     if (q->precision == QS_C64)
         hipLaunchKernelGGL(k_tile_step<float>, dim3(grid), dim3(block), lds, q->stream, (float2 *)q->amps, ta, ph, ops,
                            (const float2 *)mats);

@@ -72,7 +72,7 @@ _SIGS = {
     "qs_apply_circuit": [_P, _P],
     "qs_apply_circuit_passes": [_P, _P, _I, _I],
     "qs_circuit_pass_info": [_P, _I, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
-                             C.POINTER(C.c_int)],
+                             C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "qs_circuit_autotune": [_P, _P, _P, _I, C.POINTER(C.c_int), _PD],
     "qs_batch_create": [_I, _PP],
     "qs_batch_destroy": [_P],
@@ -306,10 +306,11 @@ PASS_KERNELS = {0: "gadget_pairs", 1: "gadget_diag", 2: "dense_vector", 3: "dens
 
 
 def qs_circuit_pass_info(c, index):
-    k, nt, nc, m = C.c_int(), C.c_int(), C.c_int(), C.c_int()
-    check(lib.qs_circuit_pass_info(c, index, C.byref(k), C.byref(nt), C.byref(nc), C.byref(m)),
+    k, nt, nc, m, ph = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_int()
+    check(lib.qs_circuit_pass_info(c, index, C.byref(k), C.byref(nt), C.byref(nc), C.byref(m), C.byref(ph)),
           "qs_circuit_pass_info")
-    return {"kernel": PASS_KERNELS[k.value], "num_targs": nt.value, "num_ctrls": nc.value, "members": m.value}
+    return {"kernel": PASS_KERNELS[k.value], "num_targs": nt.value, "num_ctrls": nc.value, "members": m.value,
+            "phases": ph.value}
 
 
 def qs_circuit_autotune(q, c, candidates):
