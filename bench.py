@@ -96,7 +96,7 @@ def time_steps(circ, q, steps, torch):
 def time_passes(circ, q, torch):
     """One application pass by pass, each bracketed by HIP events; returns
     kernel -> [launches, total ms, amplitudes touched, flops]."""
-    n = q.num_qubits
+    n = 2 * q.num_qubits if q.density else q.num_qubits     # index bits
     real = "float" if q.precision == "c64" else "double"
     npass = circ.stats()["num_passes"]
     infos = [circ.pass_info(i) for i in range(npass)]
@@ -195,10 +195,20 @@ def dm_op_kind(op):
     return ("dm_unitary" if op["op"] == "unitary" else "kraus") + f"_{k}q"
 
 
+def path_text(k):
+    if k == 0:
+        return "one pass per operator"
+    if k <= 6:
+        return f"operators fused into dense blocks of <= {k} qubits (FP32 MFMA for 4-6 qubit blocks)"
+    return f"tile steps of 2^{k} amplitudes: each step applies its operators on chip in one HBM pass"
+
+
 def bench_density(args, torch, qs, synth):
     """14-qubit density matrix (Choi vector of 2^28 amplitudes): 300 ops of
     Haar unitaries, depolarising, damping and random Kraus maps applied as
-    superoperators, then the partial trace over 7 qubits, trace and purity."""
+    superoperators, then the partial trace over 7 qubits, trace and purity.
+    Plain: the per-operator API in complex128 and complex64.  Fused: the same
+    ops as a density circuit in complex64, compiled at the autotuned width."""
     n = 14
     ops, traced = synth.config3_circuit()
     logical = synth.count_logical_updates(ops, n, density=True)
@@ -231,27 +241,53 @@ def bench_density(args, torch, qs, synth):
             c[2] += 1 << (2 * n)                          # one pass over the Choi vector
             c[3] += 8 * (1 << (2 * k)) * (1 << (2 * n))   # 4^k x 4^k superoperator
         ab = 16 if prec == "c128" else 8
-        ta = torch.cuda.Event(enable_timing=True)
-        tb = torch.cuda.Event(enable_timing=True)
-        ta.record(q.stream)
-        red = q.partial_trace(traced)
-        tb.record(q.stream)
-        tb.synchronize()
-        tr, pur = q.trace(), q.purity()
         out[prec] = {"value": logical / step_s, "ms_per_step": step_s * 1e3,
-                     "roofline": roofline(kinds, ab, n),
-                     "per_kind": per_kernel_table(kinds, ab),
-                     "partial_trace_ms": ta.elapsed_time(tb),
-                     "trace": [tr.real, tr.imag], "purity": [pur.real, pur.imag],
-                     "reduced_trace": red.trace().real, "reduced_purity": red.purity().real}
-        del q, red
-    head = out["c64"]
-    return base_line(head["value"], "amplitude-updates/s", args.steps, args.warmup, head["ms_per_step"],
+                     "roofline": roofline(kinds, ab, 2 * n),
+                     "per_kind": per_kernel_table(kinds, ab)}
+        if prec == "c128":
+            # reference result of the plain FP64 path, from |0><0|, one application
+            q.init_zero().run_ops(ops)
+            ref = q.tensor.clone()
+        del q
+
+    # fused complex64 density circuit
+    q = qs.Qureg(n, density=True, precision="c64")
+    circ = qs.Circuit(n, ops, density=True)
+    cands = tuple(int(x) for x in args.fuse_candidates.split(","))
+    best_k, tune_ms = circ.autotune(q, cands)
+    q.init_zero()
+    for _ in range(args.warmup):
+        circ.apply(q)
+    step_s = time_steps(circ, q, args.steps, torch)
+    kinds = time_passes(circ, q, torch)
+    q.init_zero()
+    circ.apply(q)
+    with torch.no_grad():
+        err = ((q.tensor.to(torch.complex128) - ref).abs().max() / ref.abs().max()).item()
+    ta = torch.cuda.Event(enable_timing=True)
+    tb = torch.cuda.Event(enable_timing=True)
+    ta.record(q.stream)
+    red = q.partial_trace(traced)
+    tb.record(q.stream)
+    tb.synchronize()
+    tr, pur = q.trace(), q.purity()
+    st = circ.stats()
+    fused = {"value": logical / step_s, "ms_per_step": step_s * 1e3, "fuse_k": best_k,
+             "autotune_ms": {str(k): v for k, v in tune_ms.items()}, "passes": st["num_passes"],
+             "max_amp_err_vs_c128": err, "per_kernel": per_kernel_table(kinds, 8),
+             "partial_trace_ms": ta.elapsed_time(tb),
+             "trace": [tr.real, tr.imag], "purity": [pur.real, pur.imag],
+             "reduced_trace": red.trace().real, "reduced_purity": red.purity().real}
+    line = base_line(fused["value"], "amplitude-updates/s", args.steps, args.warmup, fused["ms_per_step"],
                      "c64 (f32)", "14-qubit density matrix (28-qubit Choi vector), 300 seeded ops: Haar 1/2-qubit "
                      "unitaries, depolarising, damping, random 2-qubit Kraus maps as superoperators; "
                      "partial trace over 7 qubits, trace, purity",
-                     {"roofline": head["roofline"], "c64": out["c64"], "c128": out["c128"],
-                      "speedup_c64_vs_c128": out["c128"]["ms_per_step"] / out["c64"]["ms_per_step"]})
+                     {"roofline": roofline(kinds, 8, 2 * n), "fused_c64": fused,
+                      "plain_c128": out["c128"], "plain_c64": out["c64"],
+                      "speedup_fused_c64_vs_plain_c128": out["c128"]["ms_per_step"] / fused["ms_per_step"]})
+    line["config"]["path"] = "complex64 density circuit, " + path_text(best_k)
+    del q, red
+    return line
 
 
 def bench_batch(args, torch, qs, synth):
@@ -380,8 +416,7 @@ def main():
         "config": {"workload": f"{n}-qubit statevector, {len(ops)}-gate random circuit (Haar 1q, "
                                "2-target Haar with 0-3 controls, Pauli gadgets of weight 1-N)",
                    "num_qubits": n, "gates": len(ops),
-                   "path": f"complex64, gates fused into dense blocks of <= {best_k} qubits (autotuned), "
-                           "FP32 MFMA for 4-6 qubit blocks"},
+                   "path": f"complex64, {path_text(best_k)} (fusion width autotuned)"},
         "roofline": roofline(kinds64, 8, n),
         "fused_c64": {"value": logical / t64, "ms_per_step": t64 * 1e3, "fuse_k": best_k,
                       "autotune_ms": {str(k): v for k, v in tune_ms.items()},

@@ -200,27 +200,51 @@ int qs_calc_inner_product(const qs_qureg *a, const qs_qureg *b, double *out_re, 
 /* ---- circuits: recorded op lists, optionally fused into dense blocks ------- */
 
 /*
- * A circuit records statevector operators for later application.  Compiling
- * it with fuse_k >= 2 merges operators into dense blocks of at most fuse_k
- * qubits (2 <= fuse_k <= 6): an operator joins the current block when the
- * block's qubit set stays within fuse_k qubits and the operator commutes
- * with every operator it is moved across (disjoint qubits).  A block's matrix
- * is the FP64 product of its members, each written densely on the block's
- * qubits (controls expanded, a gadget as cos(theta) 1 + i sin(theta) P, Sec.
- * "Pauli gadget").  Operators on more than fuse_k qubits stay single passes.
+ * A circuit records operators for later application.  A statevector
+ * circuit holds gates and Pauli gadgets on N qubits; a density circuit
+ * (qs_circuit_create_density) holds them for an N-qubit density matrix and
+ * records each as the Choi-vector operators of Sec. "density matrices"
+ * (U on the row qubits t, conj(U) on the column qubits t + N; a gadget on t
+ * and again on t + N with the conjugate's angle), plus superoperators and
+ * Kraus maps on (t, t + N).  Compiling plans passes over the 2N index bits.
+ *
  * fuse_k = 0 keeps one pass per operator (the plain per-gate method).
+ * 2 <= fuse_k <= 6 merges operators into dense blocks of at most fuse_k
+ * qubits: an operator joins the current block when the block's qubit set
+ * stays within fuse_k qubits and the operator commutes with every operator
+ * it is moved across (disjoint qubits).  A block's matrix is the FP64
+ * product of its members, each written densely on the block's qubits
+ * (controls expanded, a gadget as cos(theta) 1 + i sin(theta) P, Sec.
+ * "Pauli gadget").  Operators on more than fuse_k qubits stay single passes.
  * Blocks of 4-6 qubits on complex64 run as FP32 MFMA GEMMs.
+ * 8 <= fuse_k <= 13 plans tile steps of at most 2^fuse_k amplitudes (a
+ * coset of a GF(2) subspace of the index space holding the lowest qubits,
+ * every target of a member gate and every gadget's X/Y flip mask): each
+ * step reads the state once, applies all its members on chip, and writes it
+ * once.  Gates of up to 3 targets and 4 controls, and gadgets of any
+ * weight, join steps; other operators stay single passes.  The largest
+ * fuse_k a device allows depends on its LDS per block (2^fuse_k amplitudes).
+ *
  * The circuit owns device copies of its matrices for one precision; it must
  * outlive the work queued by qs_apply_circuit.
  */
 int qs_circuit_create(int num_qubits, qs_circuit **out);
+/* Density circuit for an N-qubit density matrix, 1 <= N <= 20. */
+int qs_circuit_create_density(int num_qubits, qs_circuit **out);
 int qs_circuit_destroy(qs_circuit *c);
 /* Same arguments and meaning as qs_apply_multi_ctrl_multi_targ_unitary. */
 int qs_circuit_add_unitary(qs_circuit *c, const int *ctrls, int num_ctrls, const int *targs, int num_targs,
                            const double *matrix);
 /* Same arguments and meaning as qs_apply_pauli_gadget. */
 int qs_circuit_add_pauli_gadget(qs_circuit *c, const int *targs, const int *paulis, int num_targs, double theta);
-/* Builds the pass list (see above); precision selects the device matrix layout. */
+/* Density circuits only (QS_E_PRECOND otherwise); same arguments and
+ * meaning as qs_apply_superop and qs_apply_kraus_map (the Kraus map is
+ * stored as its superoperator, built in FP64). */
+int qs_circuit_add_superop(qs_circuit *c, const int *targs, int num_targs, const double *superop);
+int qs_circuit_add_kraus_map(qs_circuit *c, const int *targs, int num_targs, const double *kraus, int num_ops);
+/* Builds the pass list (see above); precision selects the device matrix
+ * layout.  QS_E_ARG for a fuse_k outside 0, 2..6, 8..13 or beyond the
+ * device's tile limit. */
 int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision);
 /* Pass statistics of the compiled circuit; any pointer may be NULL.
  * logical_updates: amplitude updates under the plain per-gate accounting
@@ -229,8 +253,9 @@ int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision);
  * 0 counts single gadget passes). */
 int qs_circuit_stats(const qs_circuit *c, int *num_ops, int *num_passes, uint64_t *logical_updates,
                      int *blocks_by_width);
-/* Applies the compiled circuit to a statevector of the circuit's size and
- * compiled precision, in order, on the qureg's stream. */
+/* Applies the compiled circuit to a qureg of the circuit's size, kind
+ * (statevector or density matrix) and compiled precision, in order, on the
+ * qureg's stream. */
 int qs_apply_circuit(qs_qureg *q, qs_circuit *c);
 
 /* Applies passes [first, first + count) of the compiled circuit (same rules

@@ -1,24 +1,34 @@
-"""Circuit: a recorded list of statevector operators, compiled once (plain
-per-gate passes, or dense k-qubit blocks) and applied through the C ABI."""
+"""Circuit: a recorded list of operators on a statevector or a density
+matrix, compiled once (plain per-gate passes, dense k-qubit blocks, or tile
+steps) and applied through the C ABI."""
 from . import native as N
 
 
 class Circuit:
-    def __init__(self, num_qubits, ops=()):
+    def __init__(self, num_qubits, ops=(), density=False):
         self.num_qubits = int(num_qubits)
-        self._c = N.qs_circuit_create(self.num_qubits)
+        self.density = bool(density)
+        self._c = (N.qs_circuit_create_density if self.density else N.qs_circuit_create)(self.num_qubits)
         self.compiled_for = None
         for op in ops:
             self.add(op)
 
     def add(self, op):
-        """Append an op dict ({"op": "unitary"|"gadget", ...})."""
-        if op["op"] == "unitary":
-            N.qs_circuit_add_unitary(self._c, op["ctrls"], op["targs"], op["matrix"])
-        elif op["op"] == "gadget":
+        """Append an op dict ({"op": "unitary"|"gadget", ...}; density
+        circuits also take "kraus" and "superop")."""
+        kind = op["op"]
+        if kind == "unitary":
+            N.qs_circuit_add_unitary(self._c, op.get("ctrls", ()), op["targs"], op["matrix"])
+        elif kind == "gadget":
             N.qs_circuit_add_pauli_gadget(self._c, op["targs"], op["paulis"], op["theta"])
+        elif kind in ("kraus", "superop") and not self.density:
+            raise ValueError(f"{kind} operators belong to density circuits")
+        elif kind == "kraus":
+            N.qs_circuit_add_kraus_map(self._c, op["targs"], op["kraus"])
+        elif kind == "superop":
+            N.qs_circuit_add_superop(self._c, op["targs"], op["matrix"])
         else:
-            raise ValueError(f"circuits hold statevector operators, not {op['op']}")
+            raise ValueError(f"unknown op {kind}")
         self.compiled_for = None
         return self
 

@@ -146,7 +146,7 @@ static void fuse(qs_circuit *c, int k)
                     blocked |= sj;
                 }
             }
-            if (__builtin_popcountll(blocked) >= c->num_qubits) break;
+            if (__builtin_popcountll(blocked) >= c->index_bits) break;
         }
         if (members.size() == 1) {
             c->passes.push_back(single_pass(c->ops[i]));
@@ -177,6 +177,19 @@ int qs_circuit_create(int num_qubits, qs_circuit **out)
     *out = new (std::nothrow) qs_circuit{};
     if (!*out) return fail(QS_E_ALLOC, "host allocation failed");
     (*out)->num_qubits = num_qubits;
+    (*out)->index_bits = num_qubits;
+    return QS_OK;
+}
+
+int qs_circuit_create_density(int num_qubits, qs_circuit **out)
+{
+    if (!out) return fail(QS_E_ARG, "null output pointer");
+    if (num_qubits < 1 || num_qubits > 20) return fail(QS_E_ARG, "qubit count out of range");
+    *out = new (std::nothrow) qs_circuit{};
+    if (!*out) return fail(QS_E_ALLOC, "host allocation failed");
+    (*out)->num_qubits = num_qubits;
+    (*out)->is_density = 1;
+    (*out)->index_bits = 2 * num_qubits;
     return QS_OK;
 }
 
@@ -205,7 +218,18 @@ int qs_circuit_add_unitary(qs_circuit *c, const int *ctrls, int num_ctrls, const
     const size_t D = (size_t)1 << num_targs;
     op.M.resize(D * D);
     for (size_t i = 0; i < D * D; i++) op.M[i] = cd(matrix[2 * i], matrix[2 * i + 1]);
-    c->ops.push_back(std::move(op));
+    if (c->is_density) {
+        // U on (c, t) of the Choi vector, then conj(U) on (c + N, t + N)
+        // (Sec. "density matrices", unitaries on the Choi vector)
+        CircOp hi = op;
+        for (int &x : hi.ctrls) x += c->num_qubits;
+        for (int &x : hi.targs) x += c->num_qubits;
+        for (auto &x : hi.M) x = std::conj(x);
+        c->ops.push_back(std::move(op));
+        c->ops.push_back(std::move(hi));
+    } else {
+        c->ops.push_back(std::move(op));
+    }
     c->compiled = false;
     return QS_OK;
 }
@@ -222,9 +246,61 @@ int qs_circuit_add_pauli_gadget(qs_circuit *c, const int *targs, const int *paul
     op.targs.assign(targs, targs + num_targs);
     op.paulis.assign(paulis, paulis + num_targs);
     op.theta = theta;
+    if (c->is_density) {
+        // conj(exp(i theta P)) = exp(i (-1)^(m+1) theta P), m = #Y, on t + N
+        CircOp hi = op;
+        hi.theta = -theta;
+        for (int x : hi.paulis)
+            if (x == 2) hi.theta = -hi.theta;
+        for (int &x : hi.targs) x += c->num_qubits;
+        c->ops.push_back(std::move(op));
+        c->ops.push_back(std::move(hi));
+    } else {
+        c->ops.push_back(std::move(op));
+    }
+    c->compiled = false;
+    return QS_OK;
+}
+
+// A superoperator S (4^n x 4^n) on the Choi vector's qubits (t, t + N).
+static int add_superop_matrix(qs_circuit *c, const int *targs, int num_targs, std::vector<cd> S)
+{
+    CircOp op{};
+    op.gadget = false;
+    op.targs.assign(targs, targs + num_targs);
+    for (int i = 0; i < num_targs; i++) op.targs.push_back(targs[i] + c->num_qubits);
+    op.M = std::move(S);
     c->ops.push_back(std::move(op));
     c->compiled = false;
     return QS_OK;
+}
+
+int qs_circuit_add_superop(qs_circuit *c, const int *targs, int num_targs, const double *superop)
+{
+    if (!c || !targs || !superop) return fail(QS_E_ARG, "null argument");
+    if (!c->is_density) return fail(QS_E_PRECOND, "superoperators belong to density circuits");
+    if (num_targs < 1 || num_targs > 3) return fail(QS_E_ARG, "1 to 3 targets supported");
+    std::string why;
+    if (!valid_qubits(targs, num_targs, c->num_qubits, why)) return fail(QS_E_ARG, why);
+    const size_t D = (size_t)1 << (2 * num_targs);
+    std::vector<cd> S(D * D);
+    for (size_t i = 0; i < D * D; i++) S[i] = cd(superop[2 * i], superop[2 * i + 1]);
+    return add_superop_matrix(c, targs, num_targs, std::move(S));
+}
+
+int qs_circuit_add_kraus_map(qs_circuit *c, const int *targs, int num_targs, const double *kraus, int num_ops)
+{
+    if (!c || !targs || !kraus) return fail(QS_E_ARG, "null argument");
+    if (!c->is_density) return fail(QS_E_PRECOND, "Kraus maps belong to density circuits");
+    if (num_targs < 1 || num_targs > 3) return fail(QS_E_ARG, "1 to 3 targets supported");
+    if (num_ops < 1) return fail(QS_E_ARG, "need at least one Kraus operator");
+    std::string why;
+    if (!valid_qubits(targs, num_targs, c->num_qubits, why)) return fail(QS_E_ARG, why);
+    const size_t d = (size_t)1 << num_targs;
+    std::vector<std::vector<cd>> ks(num_ops, std::vector<cd>(d * d));
+    for (int m = 0; m < num_ops; m++)
+        for (size_t i = 0; i < d * d; i++) ks[m][i] = cd(kraus[2 * (m * d * d + i)], kraus[2 * (m * d * d + i) + 1]);
+    return add_superop_matrix(c, targs, num_targs, superop_of_kraus(ks, num_targs));
 }
 
 int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision)
@@ -297,7 +373,7 @@ int qs_circuit_stats(const qs_circuit *c, int *num_ops, int *num_passes, uint64_
     if (logical_updates) {
         uint64_t u = 0;
         for (const auto &op : c->ops)
-            u += op.gadget ? (1ULL << c->num_qubits) : (1ULL << (c->num_qubits - (int)op.ctrls.size()));
+            u += op.gadget ? (1ULL << c->index_bits) : (1ULL << (c->index_bits - (int)op.ctrls.size()));
         *logical_updates = u;
     }
     if (blocks_by_width) {
@@ -331,6 +407,7 @@ uint64_t circuit_fingerprint(const qs_circuit *c)
         }
     };
     mix(&c->num_qubits, sizeof(int));
+    mix(&c->is_density, sizeof(int));
     for (const auto &op : c->ops) {
         mix(&op.gadget, sizeof(bool));
         for (int x : op.ctrls) mix(&x, sizeof(int));
@@ -372,7 +449,7 @@ int qs_circuit_pass_info(const qs_circuit *c, int index, int *kernel, int *num_t
     } else {
         nt = (int)p.sorted_targs.size();
         nc = (int)p.ctrls.size();
-        const uint64_t groups = 1ULL << (c->num_qubits - nt - nc);
+        const uint64_t groups = 1ULL << (c->index_bits - nt - nc);
         const bool mfma = p.kernel == kDenseMfma && c->precision == QS_C64 && nt >= 4 && groups >= 16;
         k = mfma ? 3 : 2;
     }
@@ -387,7 +464,9 @@ int qs_circuit_pass_info(const qs_circuit *c, int index, int *kernel, int *num_t
 int qs_apply_circuit_passes(qs_qureg *q, qs_circuit *c, int first, int count)
 {
     if (!q || !c) return fail(QS_E_ARG, "null argument");
-    if (q->is_density) return fail(QS_E_PRECOND, "circuits apply to statevectors");
+    if (q->is_density != c->is_density)
+        return fail(QS_E_PRECOND, c->is_density ? "density circuits apply to density matrices"
+                                                : "statevector circuits apply to statevectors");
     if (q->num_qubits != c->num_qubits) return fail(QS_E_ARG, "qubit counts differ");
     if (!c->compiled) return fail(QS_E_PRECOND, "circuit is not compiled");
     if (c->precision != q->precision) return fail(QS_E_TYPE, "circuit compiled for the other precision");

@@ -109,6 +109,8 @@ Pass single_pass(const CircOp &op);
 
 struct qs_circuit {
     int num_qubits;
+    int is_density = 0;    // ops act on the Choi vector of an N-qubit density matrix
+    int index_bits = 0;    // N, or 2N for a density circuit: the qubits ops address
     std::vector<qs::CircOp> ops;
     std::vector<qs::Pass> passes;
     bool compiled = false;

@@ -320,7 +320,7 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
 
 void plan_tiles(qs_circuit *c, int T, int precision)
 {
-    const int N = c->num_qubits;
+    const int N = c->index_bits;
     const int n_ops = (int)c->ops.size();
     const int C = std::min(N, precision == QS_C64 ? 4 : 3);
     T = std::min(T, N);

@@ -64,6 +64,9 @@ _SIGS = {
     "qs_calc_purity": [_P, _PD, _PD],
     "qs_calc_inner_product": [_P, _P, _PD, _PD],
     "qs_circuit_create": [_I, _PP],
+    "qs_circuit_create_density": [_I, _PP],
+    "qs_circuit_add_superop": [_P, _P, _I, _P],
+    "qs_circuit_add_kraus_map": [_P, _P, _I, _P, _I],
     "qs_circuit_destroy": [_P],
     "qs_circuit_add_unitary": [_P, _P, _I, _P, _I, _P],
     "qs_circuit_add_pauli_gadget": [_P, _P, _P, _I, _D],
@@ -262,6 +265,28 @@ def qs_circuit_create(num_qubits):
     out = C.c_void_p()
     check(lib.qs_circuit_create(num_qubits, C.byref(out)), "qs_circuit_create")
     return out
+
+
+def qs_circuit_create_density(num_qubits):
+    out = C.c_void_p()
+    check(lib.qs_circuit_create_density(num_qubits, C.byref(out)), "qs_circuit_create_density")
+    return out
+
+
+def qs_circuit_add_superop(c, targs, superop):
+    t = ints(targs)
+    _square(superop, 1 << (2 * t.size), "superoperator")
+    s = cmatrix(superop)
+    check(lib.qs_circuit_add_superop(c, ptr(t), t.size, ptr(s)), "qs_circuit_add_superop")
+
+
+def qs_circuit_add_kraus_map(c, targs, kraus):
+    t = ints(targs)
+    k = np.ascontiguousarray(np.asarray(kraus, dtype=np.complex128))
+    if k.ndim != 3 or k.shape[1:] != (1 << t.size, 1 << t.size):
+        raise ValueError(f"Kraus operators must have shape (M, {1 << t.size}, {1 << t.size})")
+    check(lib.qs_circuit_add_kraus_map(c, ptr(t), t.size, ptr(k.view(np.float64)), k.shape[0]),
+          "qs_circuit_add_kraus_map")
 
 
 def qs_circuit_destroy(c):

@@ -64,3 +64,32 @@ def test_binding_rejects_bad_shapes():
         N.qs_apply_superop(None, [0], np.eye(2))
     with pytest.raises(ValueError):
         N.qs_apply_pauli_gadget(None, [0, 1], [1], 0.2)
+
+
+def test_circuit_recording_checks(lib):
+    """Circuit creation and recording are host-only: kinds, sizes, qubits."""
+    from paper_2311_01512_amd import native as N
+    import numpy as np
+    with pytest.raises(ValueError):
+        N.qs_circuit_create_density(21)                      # 2^42 Choi amplitudes
+    c = N.qs_circuit_create(3)
+    try:
+        with pytest.raises(ValueError, match="density"):
+            N.qs_circuit_add_kraus_map(c, [0], np.eye(2)[None])
+        with pytest.raises(ValueError, match="density"):
+            N.qs_circuit_add_superop(c, [0], np.eye(4))
+    finally:
+        N.qs_circuit_destroy(c)
+    d = N.qs_circuit_create_density(3)
+    try:
+        N.qs_circuit_add_unitary(d, [1], [0], np.eye(2))
+        N.qs_circuit_add_pauli_gadget(d, [0, 2], [2, 3], 0.3)
+        N.qs_circuit_add_kraus_map(d, [2], np.eye(2)[None])
+        with pytest.raises(ValueError):
+            N.qs_circuit_add_superop(d, [3], np.eye(4))      # qubit 3 of 3
+        n_ops = C.c_int()
+        lib.qs_circuit_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p, C.c_void_p]
+        assert lib.qs_circuit_stats(d, C.byref(n_ops), None, None, None) == 0
+        assert n_ops.value == 5        # unitary and gadget twice (rows, columns), the map once
+    finally:
+        N.qs_circuit_destroy(d)
