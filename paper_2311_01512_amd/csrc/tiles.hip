@@ -553,19 +553,22 @@ __global__ __launch_bounds__(1024) void k_tile_step(C2<R> *__restrict__ a, TileA
     const uint64_t xs = thread_offset(t, lb, last);
     uint64_t tile = blockIdx.x;
     if (tile >= ta.num_tiles) return;
-    C2<R> nx[kRegs];
+    C2<R> x[kRegs];
     {
         const uint64_t b0 = insert_zeros(tile, ta.plan);
 #pragma unroll
-        for (int u = 0; u < kRegs; u++) nx[u] = a[b0 ^ xg ^ first.yaddr[u]];
+        for (int u = 0; u < kRegs; u++) x[u] = a[b0 ^ xg ^ first.yaddr[u]];
+        // the first tile is waited for here, so that inside the loop the
+        // only memory wait is for the prefetch, never for earlier stores
+#pragma unroll
+        for (int u = 0; u < kRegs; u++) asm volatile("" ::"v"(x[u].x), "v"(x[u].y));
     }
     for (; tile < ta.num_tiles; tile += gridDim.x) {
         const uint64_t base = insert_zeros(tile, ta.plan);
-        C2<R> x[kRegs];
-#pragma unroll
-        for (int u = 0; u < kRegs; u++) x[u] = nx[u];
         const uint64_t next = tile + gridDim.x;
-        if (next < ta.num_tiles) {
+        const bool more = next < ta.num_tiles;
+        C2<R> nx[kRegs];
+        if (more) {
             const uint64_t nb = insert_zeros(next, ta.plan);
 #pragma unroll
             for (int u = 0; u < kRegs; u++) nx[u] = a[nb ^ xg ^ first.yaddr[u]];
@@ -591,6 +594,10 @@ __global__ __launch_bounds__(1024) void k_tile_step(C2<R> *__restrict__ a, TileA
         }
 #pragma unroll
         for (int u = 0; u < kRegs; u++) a[base ^ xs ^ last.yaddr[u]] = x[u];
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < kRegs; u++) x[u] = nx[u];
+        }
     }
 }
 
