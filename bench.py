@@ -43,8 +43,9 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for hardware-counter collection: one torch copy of 2 GiB "
                          "(the calibration kernel of known traffic), then one application of the "
-                         "fused complex64 circuit")
-    ap.add_argument("--probe-fuse-k", type=int, default=5)
+                         "28-qubit circuit compiled at --probe-fuse-k in --probe-precision")
+    ap.add_argument("--probe-fuse-k", type=int, default=12)
+    ap.add_argument("--probe-precision", default="c64", choices=["c64", "c128"])
     ap.add_argument("--workload", default="circuit28", choices=["circuit28", "density14", "batch512", "sv34"],
                     help="circuit28 (default, the headline): 28-qubit 500-gate circuit; density14: 14-qubit "
                          "density matrix; batch512: 512 circuits with energies and gradients; sv34: 34 qubits")
@@ -172,12 +173,12 @@ def pmc_probe(args):
     torch.cuda.synchronize()
     del src, dst
     ops = synth.config2_circuit(num_qubits=n, num_gates=args.gates)
-    q = qs.Qureg(n, precision="c64").init_hashed(11)
-    circ = qs.Circuit(n, ops).compile(args.probe_fuse_k, "c64")
+    q = qs.Qureg(n, precision=args.probe_precision).init_hashed(11)
+    circ = qs.Circuit(n, ops).compile(args.probe_fuse_k, args.probe_precision)
     circ.apply(q)
     q.sync()
     print(json.dumps({"pmc_probe": "done", "gates": len(ops), "num_qubits": n,
-                      "fuse_k": args.probe_fuse_k}), flush=True)
+                      "fuse_k": args.probe_fuse_k, "precision": args.probe_precision}), flush=True)
 
 
 def base_line(metric_value, unit, steps, warmup, ms, dtype, workload, extra):
