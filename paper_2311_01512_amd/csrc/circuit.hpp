@@ -38,12 +38,15 @@ constexpr int kRegs = 1 << kRegBits;
 constexpr int kTileDimMax = kRegBits + 10;   // 1024 threads per block
 
 // Thread t holds coordinates tau(t) ^ rho[u], u < kRegs: rho spans the
-// phase's register subspace (basis r_j with distinct highest bits, the
-// pivots), and tau deposits the bits of t, in order, at the coordinates
-// that are not pivots.
+// phase's register subspace (basis r_j, each with its own pivot bit), and
+// tau deposits the bits of t, in order, at the coordinates that are not
+// pivots.  In a phase with matrix-core operators (c4 >= 0) bits 4 and 5 of t
+// go to the lane coordinates c4 and c5 instead, and the other bits skip them.
 struct RPhase {
     uint32_t rho[kRegs];
-    uint32_t lo[kRegBits];          // (1 << pivot) - 1, pivots ascending
+    uint32_t lo[kRegBits + 2];      // (1 << q) - 1 for the pivots and lane coordinates, ascending
+    int nlo;                        // kRegBits, or kRegBits + 2 with lane coordinates
+    int c4, c5;
     uint32_t pad_;
     uint64_t yaddr[kRegs];          // index offset of rho[u] (xor of w_k)
     uint64_t taddr[kTileDimMax];    // index offset of thread bit k
@@ -59,6 +62,9 @@ struct RPhase {
 //              with u ^ (code - 8).  Sign parity of element (t, u) is
 //              parity(base & yz) ^ parity(tau & yzm) ^ parity(u & gy); the
 //              partner's sign is folded into (pre, pim).
+//   code 32..38: dense gate on the matrix cores (complex64): targets on the
+//              lane coordinates c4, c5 and the register bits set in code - 32;
+//              mat indexes its per-lane MFMA coefficients; controls as above.
 struct ROp {
     int code;
     int nc;
@@ -68,7 +74,7 @@ struct ROp {
     uint64_t yz;
     uint32_t yzm, gy;
     int mat;                        // first entry of its matrix in the table
-    int pad_;
+    uint32_t hsel;                  // matrix-core gate: 2 bits per register, rho[u] at (c4, c5)
     double cs, cre, cim;            // gadget: cos(theta), i sin(theta) i^{#Y}
     double pre, pim;                // (cre, cim) times (-1)^parity(x & yz)
 };

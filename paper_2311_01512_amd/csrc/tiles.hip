@@ -24,6 +24,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 namespace qs {
 
@@ -58,7 +59,12 @@ struct Echelon {
     }
 };
 
-static bool absorbable(const CircOp &op) { return op.gadget || op.targs.size() <= 3; }
+// Gates of up to 3 targets run on registers; 4-target gates only on the
+// matrix cores (complex64 tiles of at least 2^9 amplitudes).
+static bool absorbable(const CircOp &op, bool mfma)
+{
+    return op.gadget || op.targs.size() <= 3 || (mfma && op.targs.size() == 4);
+}
 
 static std::vector<uint64_t> needed_vectors(const CircOp &op)
 {
@@ -98,46 +104,101 @@ int tile_dim_limit(int precision)
 // ---- phases -----------------------------------------------------------------------------
 
 // Register basis of a phase in tile coordinates: the unit vectors of the
-// dense targets first, then the gadget flips reduced to new highest bits,
-// then (if pad) unit vectors of the highest free coordinates up to kRegBits.
-// Every vector has its own highest bit, so the set is independent and
-// completes to a basis with the unit vectors of the other coordinates.
-static int reg_basis(const std::vector<int> &units, const std::vector<uint32_t> &flips, int d, bool pad,
-                     std::vector<uint32_t> &r)
+// register targets first, then the gadget flips reduced against what is
+// there, then (if pad) unit vectors of the highest free coordinates up to
+// kRegBits.  A vector's pivot is its highest set bit outside `excl` (the
+// lane coordinates of an MFMA phase); every vector has no free bit above its
+// pivot, so the set is independent of itself and of the unit vectors of all
+// other coordinates.  Returns the number of vectors, or -1 when a target
+// is excluded or a flip lies in span(r) + span(excl) but not in span(r).
+static int reg_basis(const std::vector<int> &units, const std::vector<uint32_t> &flips, uint32_t excl, int d,
+                     bool pad, std::vector<uint32_t> &r, std::vector<int> &piv)
 {
     r.clear();
-    uint32_t umask = 0;
-    for (int c : units)
-        if (!((umask >> c) & 1u)) {
-            umask |= 1u << c;
-            r.push_back(1u << c);
-        }
-    std::vector<uint32_t> g;
+    piv.clear();
+    auto reduce = [&](uint32_t x) {
+        std::vector<size_t> order(r.size());
+        for (size_t j = 0; j < r.size(); j++) order[j] = j;
+        std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return piv[a] > piv[b]; });
+        for (size_t j : order)
+            if ((x >> piv[j]) & 1u) x ^= r[j];
+        return x;
+    };
+    for (int c : units) {
+        if ((excl >> c) & 1u) return -1;
+        if (std::find(piv.begin(), piv.end(), c) != piv.end()) continue;
+        r.push_back(1u << c);
+        piv.push_back(c);
+    }
     for (uint32_t f : flips) {
-        uint32_t x = f & ~umask;
-        while (x) {
-            const int hb = 31 - __builtin_clz(x);
-            auto it = std::find_if(g.begin(), g.end(), [&](uint32_t y) { return 31 - __builtin_clz(y) == hb; });
-            if (it == g.end()) break;
-            x ^= *it;
+        const uint32_t x = reduce(f);
+        if (!x) continue;
+        const uint32_t free_bits = x & ~excl;
+        if (!free_bits) return -1;
+        r.push_back(x);
+        piv.push_back(31 - __builtin_clz(free_bits));
+    }
+    if (pad)
+        for (int c = d - 1; c >= 0 && (int)r.size() < kRegBits; c--) {
+            if (((excl >> c) & 1u) || std::find(piv.begin(), piv.end(), c) != piv.end()) continue;
+            r.push_back(1u << c);
+            piv.push_back(c);
         }
-        if (x) g.push_back(x);
-    }
-    r.insert(r.end(), g.begin(), g.end());
-    if (pad) {
-        uint32_t piv = 0;
-        for (uint32_t v : r) piv |= 1u << (31 - __builtin_clz(v));
-        for (int c = d - 1; c >= 0 && (int)r.size() < kRegBits; c--)
-            if (!((piv >> c) & 1u)) {
-                r.push_back(1u << c);
-                piv |= 1u << c;
-            }
-    }
     return (int)r.size();
 }
 
+// A phase under construction: lane coordinates of its MFMA operators (or
+// none), register target coordinates, gadget flips.
+struct PhaseBuild {
+    int c4 = -1, c5 = -1;
+    std::vector<int> units;
+    std::vector<uint32_t> flips;
+    uint32_t excl() const { return c4 < 0 ? 0u : ((1u << c4) | (1u << c5)); }
+    bool fits() const
+    {
+        std::vector<uint32_t> r;
+        std::vector<int> piv;
+        const int n = reg_basis(units, flips, excl(), 32, false, r, piv);
+        return n >= 0 && n <= kRegBits;
+    }
+};
+
+// Real coefficients of a k-target gate (k = 2, 3, 4) for v_mfma_f32_16x16x4f32.
+// Lane L of the wavefront holds, in register u, the element whose lane
+// coordinates c4, c5 carry g ^ h(u) (g = L / 16; h(u) = the bits of rho[u] at
+// c4, c5) in group L % 16, and further members in registers for the register-
+// target bits rho; member index i = (g ^ h) + 4 rho.  K-step s feeds the real
+// (s even) or imaginary part of register rho = s / 2; output block b,
+// register i of lane group g' receives component o = 4 b + i, i.e. the real
+// (o even) or imaginary part of member (g' ^ h) + 4 (o / 2).  Lane L supplies
+// A[L % 16][L / 16] of each (b, s).  Layout: [h][lane][b][s], NB * KS floats
+// per lane, four variants h = 0..3.
+static void mfma_coeffs(const std::vector<cd> &G, int k, std::vector<cd> &out)
+{
+    const int R = 1 << (k - 2), KS = 2 * R, NB = R >= 2 ? R / 2 : 1;
+    const int D = 1 << k;
+    std::vector<float> a((size_t)4 * 64 * NB * KS, 0.f);
+    for (int h = 0; h < 4; h++)
+        for (int L = 0; L < 64; L++) {
+            const int m = L % 16, gp = m / 4, i = m % 4, g = L / 16;
+            for (int b = 0; b < NB; b++)
+                for (int s = 0; s < KS; s++) {
+                    const int o = 4 * b + i;
+                    float v = 0.f;
+                    if (o < 2 * R) {
+                        const int iout = (gp ^ h) + 4 * (o / 2), iin = (g ^ h) + 4 * (s / 2);
+                        const cd z = G[(size_t)iout * D + iin];
+                        const int po = o % 2, pi = s % 2;
+                        v = (float)(po == pi ? z.real() : (po ? z.imag() : -z.imag()));
+                    }
+                    a[((size_t)h * 64 + L) * NB * KS + b * KS + s] = v;
+                }
+        }
+    for (size_t j = 0; j < a.size(); j += 2) out.push_back(cd(a[j], a[j + 1]));
+}
+
 // Operators of a finished step in the step's coordinates, grouped in phases.
-static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircOp *> &members)
+static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircOp *> &members, bool mfma)
 {
     p.tile = true;
     p.gadget = false;
@@ -149,6 +210,8 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
     }
     const int d = (int)p.basis.size();
     p.tile_d = d;
+    const int lb = d - kRegBits;
+    mfma = mfma && lb >= 6;   // lane bits 4 and 5 must exist, every wave full
     auto coord_of_pivot = [&](int b) {
         return (int)(std::find(p.pivots.begin(), p.pivots.end(), b) - p.pivots.begin());
     };
@@ -197,53 +260,96 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
             for (int t : op->targs) n.units.push_back(coord_of_pivot(t));
         }
     }
+    // Fits member m into phase B: a gadget by its flip; a dense gate of <= 3
+    // targets in registers; a gate of 3-4 targets that does not fit there on
+    // the matrix cores (two targets on the lane coordinates, the rest in
+    // registers).  Gates of 2-3 targets measured no faster on the matrix cores
+    // (a 2-target gate as a real 8 x 8 product fills half of the 16 x 16
+    // tile), so the matrix cores are what lets 4-target gates (two-qubit
+    // superoperators) join a step.  Returns the mode (0 registers, 1 MFMA) or -1.
+    auto try_fit = [&](PhaseBuild &B, size_t m) {
+        const Need &n = needs[m];
+        const CircOp *op = members[m];
+        if (op->gadget) {
+            PhaseBuild T = B;
+            if (n.flip) T.flips.push_back(n.flip);
+            if (!T.fits()) return -1;
+            B = T;
+            return 0;
+        }
+        const int nt = (int)n.units.size();
+        if (nt <= 3) {
+            PhaseBuild T = B;
+            T.units.insert(T.units.end(), n.units.begin(), n.units.end());
+            if (T.fits()) {
+                B = T;
+                return 0;
+            }
+        }
+        if (!mfma || nt < 3) return -1;
+        std::vector<int> us = n.units;
+        std::sort(us.begin(), us.end());
+        PhaseBuild T = B;
+        std::vector<int> rest;
+        if (T.c4 < 0) {
+            T.c4 = us[0];
+            T.c5 = us[1];
+            rest.assign(us.begin() + 2, us.end());
+        } else {
+            if (std::find(us.begin(), us.end(), T.c4) == us.end() || std::find(us.begin(), us.end(), T.c5) == us.end())
+                return -1;
+            for (int c : us)
+                if (c != T.c4 && c != T.c5) rest.push_back(c);
+        }
+        T.units.insert(T.units.end(), rest.begin(), rest.end());
+        if (!T.fits()) return -1;
+        B = T;
+        return 1;
+    };
     const cd eta[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
     p.phases.clear();
     p.rops.clear();
     p.tmats.clear();
-    const int lb = d - kRegBits;
-    // A phase takes, in order, every remaining member that fits its register
-    // space and shares no qubit with a remaining member it jumps over.
+    // A phase takes, in order, every remaining member that fits it and shares
+    // no qubit with a remaining member it jumps over.
     std::vector<size_t> remaining(members.size());
     for (size_t m = 0; m < members.size(); m++) remaining[m] = m;
     while (!remaining.empty()) {
-        std::vector<int> units;
-        std::vector<uint32_t> flips, r;
+        PhaseBuild B;
         std::vector<size_t> chosen, rest;
+        std::vector<int> mode;
         uint64_t blocked = 0;
         for (size_t m : remaining) {
             const uint64_t s = support_mask(*members[m]);
-            bool take = false;
-            if (!(s & blocked)) {
-                std::vector<int> u2 = units;
-                std::vector<uint32_t> f2 = flips;
-                u2.insert(u2.end(), needs[m].units.begin(), needs[m].units.end());
-                if (needs[m].flip) f2.push_back(needs[m].flip);
-                if (reg_basis(u2, f2, d, false, r) <= kRegBits) {
-                    units.swap(u2);
-                    flips.swap(f2);
-                    take = true;
-                }
-            }
-            if (take) {
+            int md = -1;
+            if (!(s & blocked)) md = try_fit(B, m);
+            if (md >= 0) {
                 chosen.push_back(m);
+                mode.push_back(md);
             } else {
                 blocked |= s;
                 rest.push_back(m);
             }
         }
         remaining.swap(rest);
-        reg_basis(units, flips, d, true, r);
+        std::vector<uint32_t> r;
+        std::vector<int> pj;
+        reg_basis(B.units, B.flips, B.excl(), d, true, r, pj);
         RPhase ph{};
-        uint32_t piv = 0;
-        int pj[kRegBits];
-        for (int b = 0; b < kRegBits; b++) {
-            pj[b] = 31 - __builtin_clz(r[b]);
-            piv |= 1u << pj[b];
+        uint32_t taken = 0;   // pivots and lane coordinates: not deposited from t in order
+        for (int b = 0; b < kRegBits; b++) taken |= 1u << pj[b];
+        std::vector<int> ins(pj.begin(), pj.end());
+        ph.c4 = ph.c5 = -1;
+        if (B.c4 >= 0) {
+            ph.c4 = B.c4;
+            ph.c5 = B.c5;
+            ins.push_back(B.c4);
+            ins.push_back(B.c5);
+            taken |= B.excl();
         }
-        std::vector<int> sorted_piv(pj, pj + kRegBits);
-        std::sort(sorted_piv.begin(), sorted_piv.end());
-        for (int b = 0; b < kRegBits; b++) ph.lo[b] = (1u << sorted_piv[b]) - 1u;
+        std::sort(ins.begin(), ins.end());
+        ph.nlo = (int)ins.size();
+        for (size_t b = 0; b < ins.size(); b++) ph.lo[b] = (1u << ins[b]) - 1u;
         for (int u = 0; u < kRegs; u++) {
             uint32_t c = 0;
             for (int b = 0; b < kRegBits; b++)
@@ -251,9 +357,16 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
             ph.rho[u] = c;
             ph.yaddr[u] = addr_of(c);
         }
-        for (int k = 0, c = 0; k < lb; k++, c++) {
-            while ((piv >> c) & 1u) c++;
+        // thread bit k -> coordinate: bits 4 and 5 to the lane coordinates of
+        // an MFMA phase, the others in order to the free coordinates
+        for (int k = 0, c = 0; k < lb; k++) {
+            if (B.c4 >= 0 && (k == 4 || k == 5)) {
+                ph.taddr[k] = p.basis[k == 4 ? B.c4 : B.c5];
+                continue;
+            }
+            while ((taken >> c) & 1u) c++;
             ph.taddr[k] = p.basis[c];
+            c++;
         }
         ph.first_op = (int)p.rops.size();
         ph.num_ops = (int)chosen.size();
@@ -262,14 +375,16 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
                 if (r[b] == (1u << coord)) return b;
             return -1;
         };
-        for (size_t m : chosen) {
+        for (size_t ci = 0; ci < chosen.size(); ci++) {
+            const size_t m = chosen[ci];
             const CircOp *op = members[m];
             const Need &n = needs[m];
             ROp ro{};
             if (op->gadget) {
                 uint32_t f = n.flip, fu = 0;
                 while (f) {
-                    const int hb = 31 - __builtin_clz(f);
+                    const uint32_t fb = f & ~B.excl();
+                    const int hb = 31 - __builtin_clz(fb);
                     int b = 0;
                     while (b < kRegBits && pj[b] != hb) b++;
                     f ^= r[b];
@@ -290,15 +405,7 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
                 ro.pre = partner * c.real();
                 ro.pim = partner * c.imag();
             } else {
-                std::vector<int> js, sorted;
-                uint32_t um = 0;
-                for (int c : n.units) {
-                    js.push_back(reg_bit_of_unit(c));
-                    um |= 1u << js.back();
-                }
-                std::vector<cd> Ms = permute_to_sorted(op->M, js, sorted);
                 ro.nc = (int)op->ctrls.size();
-                ro.code = (int)um + (ro.nc > 0 ? 16 : 0);
                 for (int q = 0; q < ro.nc; q++) {
                     ro.cq[q] = op->ctrls[q];
                     ro.cm[q] = qubit_mask(op->ctrls[q]);
@@ -308,8 +415,34 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
                     for (int q = 0; q < ro.nc; q++) nib |= (uint64_t)(__builtin_popcount(ph.rho[u] & ro.cm[q]) & 1) << q;
                     ro.qtab |= nib << (4 * u);
                 }
-                ro.mat = (int)p.tmats.size();
-                p.tmats.insert(p.tmats.end(), Ms.begin(), Ms.end());
+                // sort keys: matrix bit order of the kernel
+                std::vector<int> keys, sorted;
+                uint32_t um = 0;
+                if (mode[ci] == 1) {
+                    for (int c : n.units) {
+                        if (c == B.c4) keys.push_back(-2);
+                        else if (c == B.c5) keys.push_back(-1);
+                        else {
+                            keys.push_back(reg_bit_of_unit(c));
+                            um |= 1u << keys.back();
+                        }
+                    }
+                    std::vector<cd> Ms = permute_to_sorted(op->M, keys, sorted);
+                    ro.code = 32 + (int)um;
+                    ro.mat = (int)p.tmats.size();
+                    for (int u = 0; u < kRegs; u++)
+                        ro.hsel |= (((ph.rho[u] >> B.c4) & 1u) | (((ph.rho[u] >> B.c5) & 1u) << 1)) << (2 * u);
+                    mfma_coeffs(Ms, (int)n.units.size(), p.tmats);
+                } else {
+                    for (int c : n.units) {
+                        keys.push_back(reg_bit_of_unit(c));
+                        um |= 1u << keys.back();
+                    }
+                    std::vector<cd> Ms = permute_to_sorted(op->M, keys, sorted);
+                    ro.code = (int)um + (ro.nc > 0 ? 16 : 0);
+                    ro.mat = (int)p.tmats.size();
+                    p.tmats.insert(p.tmats.end(), Ms.begin(), Ms.end());
+                }
             }
             p.rops.push_back(ro);
         }
@@ -324,6 +457,8 @@ void plan_tiles(qs_circuit *c, int T, int precision)
     const int n_ops = (int)c->ops.size();
     const int C = std::min(N, precision == QS_C64 ? 4 : 3);
     T = std::min(T, N);
+    // dense gates of 2-4 targets on the FP32 matrix cores (complex64 only)
+    const bool mfma = precision == QS_C64 && T >= kRegBits + 6;
     const int lookahead = 512;
     std::vector<char> placed(n_ops, 0);
     for (int i = 0; i < n_ops; i++) {
@@ -332,7 +467,7 @@ void plan_tiles(qs_circuit *c, int T, int precision)
         // registers need a tile of more than kRegBits dimensions; controls
         // beyond the 4 a tile operator carries, or gates of more than 3
         // targets, run as passes of their own
-        if (T <= kRegBits || !absorbable(first) || first.ctrls.size() > 4) {
+        if (T <= kRegBits || !absorbable(first, mfma) || first.ctrls.size() > 4) {
             placed[i] = 1;
             c->passes.push_back(single_pass(first));
             continue;
@@ -350,7 +485,7 @@ void plan_tiles(qs_circuit *c, int T, int precision)
                 continue;
             }
             const std::vector<uint64_t> need = needed_vectors(op);
-            if (absorbable(op) && op.ctrls.size() <= 4 && E.dim_with(need) <= T) {
+            if (absorbable(op, mfma) && op.ctrls.size() <= 4 && E.dim_with(need) <= T) {
                 for (uint64_t x : need) E.add(x);
                 members.push_back(&op);
                 placed[j] = 1;
@@ -363,7 +498,7 @@ void plan_tiles(qs_circuit *c, int T, int precision)
         // contiguous runs, fewer and larger tiles
         for (int b = C; b < N && E.dim() < T; b++) E.add(1ULL << b);
         Pass p{};
-        encode_step(p, E, members);
+        encode_step(p, E, members, mfma);
         c->passes.push_back(std::move(p));
     }
 }
@@ -416,12 +551,21 @@ __host__ __device__ constexpr int popcount_c(int m) { return m ? (m & 1) + popco
 
 __device__ __forceinline__ uint32_t tau_of(uint32_t t, const RPhase &ph)
 {
+    if (ph.nlo == kRegBits) {
 #pragma unroll
-    for (int b = 0; b < kRegBits; b++) {
-        const uint32_t lo = ph.lo[b];
-        t = (t & lo) | ((t & ~lo) << 1);
+        for (int b = 0; b < kRegBits; b++) {
+            const uint32_t lo = ph.lo[b];
+            t = (t & lo) | ((t & ~lo) << 1);
+        }
+        return t;
     }
-    return t;
+    uint32_t c = (t & 15u) | ((t >> 6) << 4);
+#pragma unroll
+    for (int b = 0; b < kRegBits + 2; b++) {
+        const uint32_t lo = ph.lo[b];
+        c = (c & lo) | ((c & ~lo) << 1);
+    }
+    return c | (((t >> 4) & 1u) << ph.c4) | (((t >> 5) & 1u) << ph.c5);
 }
 
 __device__ __forceinline__ uint64_t thread_offset(uint32_t t, int lb, const RPhase &ph)
@@ -503,10 +647,70 @@ __device__ __forceinline__ void reg_gadget(C2<R> (&x)[kRegs], const ROp &op, uin
     }
 }
 
+// Dense gate on the FP32 matrix cores.  The wavefront's 64 lanes hold 16
+// groups: lane L has member g = L / 16 of group L % 16 (g's bits are the lane
+// coordinates), and for RM != 0 further members in registers u0 | rho.  Per
+// register group one v_mfma_f32_16x16x4f32 K-step takes the real or the
+// imaginary parts of one register; the output lands in the lane that holds
+// the member (coefficients from mfma_coeffs).
+template <int RM>
+__device__ __forceinline__ void mfma_dense(float2 (&x)[kRegs], const ROp &op, uint32_t tau, uint64_t base,
+                                           const float2 *__restrict__ mats)
+{
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    constexpr int R = 1 << popcount_c(RM), KS = 2 * R, NB = R >= 2 ? R / 2 : 1;
+    const float *A0 = reinterpret_cast<const float *>(mats + op.mat) + (threadIdx.x & 63u) * (NB * KS);
+    uint32_t tp = 0;
+    for (int i = 0; i < op.nc; i++)
+        tp |= (uint32_t)(((base >> op.cq[i]) ^ (uint64_t)__popc(tau & op.cm[i])) & 1ULL) << i;
+    const uint32_t full = (1u << op.nc) - 1u;
+#pragma unroll
+    for (int u0 = 0; u0 < kRegs; u0++) {
+        if (u0 & RM) continue;
+        const bool ok = (tp ^ ((uint32_t)(op.qtab >> (4 * u0)) & 15u)) == full;
+        if (op.nc && __ballot(ok) == 0) continue;   // controls off in the whole wavefront
+        // coefficients for this register's lane-coordinate offset h(u0)
+        const float *A = A0 + ((op.hsel >> (2 * u0)) & 3u) * (64 * NB * KS);
+        float b[KS];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const float2 v = x[u0 | deposit_bits(r, RM)];
+            b[2 * r] = v.x;
+            b[2 * r + 1] = v.y;
+        }
+        // one output block (two registers' members) at a time
+#pragma unroll
+        for (int blk = 0; blk < NB; blk++) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS; s++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[blk * KS + s], b[s], acc, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; i += 2) {
+                const int r = (4 * blk + i) / 2;
+                if (r < R && ok) x[u0 | deposit_bits(r, RM)] = make_float2(acc[i], acc[i + 1]);
+            }
+        }
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ void apply_reg_op(C2<R> (&x)[kRegs], const ROp &op, uint32_t tau, uint64_t base,
                                              const C2<R> *__restrict__ mats)
 {
+    if constexpr (std::is_same<R, float>::value) {
+        if (op.code >= 32) {
+            switch (op.code) {
+            case 32: mfma_dense<0>(x, op, tau, base, mats); break;
+            case 33: mfma_dense<1>(x, op, tau, base, mats); break;
+            case 34: mfma_dense<2>(x, op, tau, base, mats); break;
+            case 35: mfma_dense<3>(x, op, tau, base, mats); break;
+            case 36: mfma_dense<4>(x, op, tau, base, mats); break;
+            case 37: mfma_dense<5>(x, op, tau, base, mats); break;
+            default: mfma_dense<6>(x, op, tau, base, mats); break;
+            }
+            return;
+        }
+    }
     const C2<R> *m = mats + op.mat;
     switch (op.code) {
     case 1: reg_dense<R, 1, false>(x, op, tau, base, m); break;

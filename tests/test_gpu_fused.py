@@ -77,12 +77,13 @@ def test_fused_circuit_parity(qs, prec, k):
     assert amp_err(q.get_amps(), want) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
 @pytest.mark.parametrize("k", [2, 3, 4, 6, 8, 9])
-def test_fusion_respects_order(qs, k):
+def test_fusion_respects_order(qs, k, prec):
     """Dense non-commuting gates on overlapping qubits, interleaved with gates
     elsewhere: blocks may only absorb ops that commute with what they skip."""
     rng = np.random.default_rng(11 + k)
-    N = 8
+    N = 10
     ops = []
     for g in range(120):
         a = int(rng.integers(0, N))
@@ -98,11 +99,45 @@ def test_fusion_respects_order(qs, k):
                         "paulis": tuple(int(x) for x in rng.integers(0, 4, size=w)), "theta": rng.uniform(-3, 3)})
     psi = synth.random_state(rng, 1 << N)
     want = oracle.run_ops(psi.copy(), ops)
-    circ = qs.Circuit(N, ops).compile(k, "c128")
-    q = qs.Qureg(N, precision="c128").set_amps(psi)
+    circ = qs.Circuit(N, ops).compile(k, prec)
+    q = qs.Qureg(N, precision=prec).set_amps(psi)
     circ.apply(q)
     # non-unitary factors grow the norm; compare relative to the largest amplitude
-    assert amp_err(q.get_amps(), want) < 1e-10
+    assert amp_err(q.get_amps(), want) < (1e-10 if prec == "c128" else 2e-5)
+
+
+@pytest.mark.parametrize("k", [9, 10, 12])
+def test_tile_matrix_core_gates(qs, k):
+    """Tile steps in complex64 with 2-, 3- and 4-target gates (the matrix-core
+    operators, two targets on lane coordinates), controls, 1-target gates and
+    gadgets interleaved."""
+    banner(f"tile mfma gates N=13 k={k}")
+    N = 13
+    rng = np.random.default_rng(300 + k)
+    ops = []
+    for g in range(160):
+        kind = g % 5
+        if kind in (0, 1, 2):
+            nt = 2 + kind
+            q = rng.permutation(N)
+            nc = int(rng.integers(0, 3))
+            ops.append({"op": "unitary", "ctrls": tuple(int(x) for x in q[nt:nt + nc]),
+                        "targs": tuple(int(x) for x in q[:nt]), "matrix": synth.haar_unitary(rng, 1 << nt)})
+        elif kind == 3:
+            ops.append({"op": "unitary", "ctrls": (), "targs": (int(rng.integers(0, N)),),
+                        "matrix": synth.haar_unitary(rng, 2)})
+        else:
+            w = int(rng.integers(1, N + 1))
+            t = rng.permutation(N)[:w]
+            ops.append({"op": "gadget", "targs": tuple(int(x) for x in t),
+                        "paulis": tuple(int(x) for x in rng.integers(1, 4, size=w)), "theta": rng.uniform(-3, 3)})
+    psi = synth.random_state(rng, 1 << N)
+    circ = qs.Circuit(N, ops).compile(k, "c64")
+    kinds = [circ.pass_info(i)["kernel"] for i in range(circ.stats()["num_passes"])]
+    assert kinds.count("tile") >= 1
+    q = qs.Qureg(N, precision="c64").set_amps(psi)
+    circ.apply(q)
+    assert amp_err(q.get_amps(), oracle.run_ops(psi.copy(), ops)) < TOL["c64"]
 
 
 def test_config5_fused_reduced(qs):
