@@ -221,9 +221,10 @@ int qs_calc_inner_product(const qs_qureg *a, const qs_qureg *b, double *out_re, 
  * coset of a GF(2) subspace of the index space holding the lowest qubits,
  * every target of a member gate and every gadget's X/Y flip mask): each
  * step reads the state once, applies all its members on chip, and writes it
- * once.  Gates of up to 3 targets and 4 controls, and gadgets of any
- * weight, join steps; other operators stay single passes.  The largest
- * fuse_k a device allows depends on its LDS per block (2^fuse_k amplitudes).
+ * once.  Gates of up to 3 targets (complex64: 4, on the matrix cores) and
+ * 4 controls, and gadgets of any weight, join steps; other operators stay
+ * single passes.  The largest fuse_k a device allows depends on its LDS per
+ * block (2^fuse_k amplitudes).
  *
  * The circuit owns device copies of its matrices for one precision; it must
  * outlive the work queued by qs_apply_circuit.
