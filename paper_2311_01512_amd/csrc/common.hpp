@@ -177,9 +177,9 @@ int mfma_preference();
 // Upper bound on the MFMA kernel's grid for a k-target gate.
 uint64_t mfma_block_cap(int k);
 
-// Threads per block forced for the LDS tile engine (QS_TILE_BLOCK), 0 if
-// the launcher chooses.
-int tile_block_size();
+// Number of lowest qubits every tile step holds (a tile is read in runs of
+// 2^this amplitudes).
+int tile_low_qubits(int precision);
 
 // Key of a recorded circuit's contents (circuit.hip).
 uint64_t circuit_fingerprint(const qs_circuit *c);

@@ -455,7 +455,7 @@ void plan_tiles(qs_circuit *c, int T, int precision)
 {
     const int N = c->index_bits;
     const int n_ops = (int)c->ops.size();
-    const int C = std::min(N, precision == QS_C64 ? 4 : 3);
+    const int C = std::min(N, tile_low_qubits(precision));
     T = std::min(T, N);
     // dense gates of 2-4 targets on the FP32 matrix cores (complex64 only)
     const bool mfma = precision == QS_C64 && T >= kRegBits + 6;

@@ -2,7 +2,8 @@
 //
 // Knobs default to values measured on MI355X and can be overridden from the
 // environment: QS_DENSE_KERNEL=vector|mfma (dense gates of 4-6 targets on
-// complex64), QS_MFMA_BLOCKS=<max blocks of the MFMA kernel>.
+// complex64), QS_MFMA_BLOCKS=<max blocks of the MFMA kernel>,
+// QS_TILE_LOW=<lowest qubits every tile step holds>.
 #include "common.hpp"
 
 #include <cstdio>
@@ -36,17 +37,18 @@ uint64_t mfma_block_cap(int)
     return cap;
 }
 
-int tile_block_size()
+int tile_low_qubits(int precision)
 {
-    static const int bs = [] {
-        const char *e = std::getenv("QS_TILE_BLOCK");
+    static const int forced = [] {
+        const char *e = std::getenv("QS_TILE_LOW");
         if (e) {
             const int v = std::atoi(e);
-            if (v == 64 || v == 128 || v == 256 || v == 512 || v == 1024) return v;
+            if (v >= 1 && v <= 8) return v;
         }
-        return 0;   // sized by the launcher
+        return 0;
     }();
-    return bs;
+    if (forced) return forced;
+    return precision == QS_C64 ? 4 : 3;   // 128-byte runs
 }
 
 // (qubits, precision, circuit fingerprint) -> chosen fusion width
