@@ -65,6 +65,9 @@ struct RPhase {
 //   code 32..38: dense gate on the matrix cores (complex64): targets on the
 //              lane coordinates c4, c5 and the register bits set in code - 32;
 //              mat indexes its per-lane MFMA coefficients; controls as above.
+//   code 64 + 4 UM + s: uncontrolled gate on register bits UM (1 or 2 of
+//              them) whose matrix couples member j only with j ^ s (s = 0:
+//              diagonal).
 struct ROp {
     int code;
     int nc;

@@ -440,6 +440,19 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
                     }
                     std::vector<cd> Ms = permute_to_sorted(op->M, keys, sorted);
                     ro.code = (int)um + (ro.nc > 0 ? 16 : 0);
+                    // uncontrolled 1-2 target gates that only couple members
+                    // i and i ^ s (diagonal: s = 0), e.g. one-qubit channels
+                    // as superoperators: the sparse form
+                    const int D = 1 << n.units.size();
+                    if (ro.nc == 0 && D <= 4) {
+                        uint32_t xs = 0;   // set of r ^ c with a nonzero entry
+                        for (int rr = 0; rr < D; rr++)
+                            for (int cc = 0; cc < D; cc++)
+                                if (Ms[(size_t)rr * D + cc] != cd(0, 0)) xs |= 1u << (rr ^ cc);
+                        xs &= ~1u;
+                        if (xs == 0 || (D == 4 && (xs & (xs - 1)) == 0))
+                            ro.code = 64 + 4 * (int)um + (xs ? __builtin_ctz(xs) : 0);
+                    }
                     ro.mat = (int)p.tmats.size();
                     p.tmats.insert(p.tmats.end(), Ms.begin(), Ms.end());
                 }
@@ -610,6 +623,29 @@ __device__ __forceinline__ void reg_dense(C2<R> (&x)[kRegs], const ROp &op, uint
     }
 }
 
+// Uncontrolled gate on the register bits UM whose matrix only couples
+// member j with j ^ SM (SM = 0: diagonal): one or two complex products per
+// amplitude instead of 2^k.
+template <typename R, int UM, int SM>
+__device__ __forceinline__ void reg_sparse(C2<R> (&x)[kRegs], const C2<R> *__restrict__ m)
+{
+    constexpr int D = 1 << popcount_c(UM);
+#pragma unroll
+    for (int u0 = 0; u0 < kRegs; u0++) {
+        if (u0 & UM) continue;
+        C2<R> in[D];
+#pragma unroll
+        for (int l = 0; l < D; l++) in[l] = x[u0 | deposit_bits(l, UM)];
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            C2<R> acc = mk<R>(R(0), R(0));
+            cmac<R>(acc, m[j * D + j], in[j]);
+            if constexpr (SM != 0) cmac<R>(acc, m[j * D + (j ^ SM)], in[j ^ SM]);
+            x[u0 | deposit_bits(j, UM)] = acc;
+        }
+    }
+}
+
 // Element (t, u) has sign parity st ^ parity(u & gy); the pair partner's
 // parity differs by parity(x & yz), folded into cre/cim on the host as a
 // second constant (ROp::pre/pim) so both outputs use the parity of u0.
@@ -698,7 +734,7 @@ __device__ __forceinline__ void apply_reg_op(C2<R> (&x)[kRegs], const ROp &op, u
                                              const C2<R> *__restrict__ mats)
 {
     if constexpr (std::is_same<R, float>::value) {
-        if (op.code >= 32) {
+        if (op.code >= 32 && op.code < 64) {
             switch (op.code) {
             case 32: mfma_dense<0>(x, op, tau, base, mats); break;
             case 33: mfma_dense<1>(x, op, tau, base, mats); break;
@@ -712,6 +748,26 @@ __device__ __forceinline__ void apply_reg_op(C2<R> (&x)[kRegs], const ROp &op, u
         }
     }
     const C2<R> *m = mats + op.mat;
+    if (op.code >= 64) {
+        switch (op.code - 64) {
+        case 4 * 1: reg_sparse<R, 1, 0>(x, m); break;
+        case 4 * 2: reg_sparse<R, 2, 0>(x, m); break;
+        case 4 * 4: reg_sparse<R, 4, 0>(x, m); break;
+        case 4 * 3: reg_sparse<R, 3, 0>(x, m); break;
+        case 4 * 3 + 1: reg_sparse<R, 3, 1>(x, m); break;
+        case 4 * 3 + 2: reg_sparse<R, 3, 2>(x, m); break;
+        case 4 * 3 + 3: reg_sparse<R, 3, 3>(x, m); break;
+        case 4 * 5: reg_sparse<R, 5, 0>(x, m); break;
+        case 4 * 5 + 1: reg_sparse<R, 5, 1>(x, m); break;
+        case 4 * 5 + 2: reg_sparse<R, 5, 2>(x, m); break;
+        case 4 * 5 + 3: reg_sparse<R, 5, 3>(x, m); break;
+        case 4 * 6: reg_sparse<R, 6, 0>(x, m); break;
+        case 4 * 6 + 1: reg_sparse<R, 6, 1>(x, m); break;
+        case 4 * 6 + 2: reg_sparse<R, 6, 2>(x, m); break;
+        default: reg_sparse<R, 6, 3>(x, m); break;
+        }
+        return;
+    }
     switch (op.code) {
     case 1: reg_dense<R, 1, false>(x, op, tau, base, m); break;
     case 2: reg_dense<R, 2, false>(x, op, tau, base, m); break;

@@ -140,6 +140,47 @@ def test_tile_matrix_core_gates(qs, k):
     assert amp_err(q.get_amps(), oracle.run_ops(psi.copy(), ops)) < TOL["c64"]
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("k", [10, 12])
+def test_tile_sparse_gates(qs, prec, k):
+    """Tile steps with the sparse register forms: diagonal 1- and 2-target
+    gates and 2-target gates coupling each member with one partner (j and
+    j ^ s), among dense gates and gadgets."""
+    banner(f"tile sparse gates N=12 k={k} {prec}")
+    N = 12
+    rng = np.random.default_rng(500 + k)
+    ops = []
+    for g in range(150):
+        kind = g % 5
+        q = [int(x) for x in rng.permutation(N)[:2]]
+        if kind == 0:
+            m = np.diag(np.exp(1j * rng.uniform(0, 6, size=2)))
+            ops.append({"op": "unitary", "ctrls": (), "targs": (q[0],), "matrix": m})
+        elif kind == 1:
+            m = np.diag(rng.normal(size=4) + 1j * rng.normal(size=4)) / 2
+            ops.append({"op": "unitary", "ctrls": (), "targs": tuple(q), "matrix": m})
+        elif kind == 2:
+            s_ = int(rng.integers(1, 4))
+            m = synth.random_matrix(rng, 4) / 2
+            for r in range(4):
+                for c in range(4):
+                    if (r ^ c) not in (0, s_):
+                        m[r, c] = 0
+            ops.append({"op": "unitary", "ctrls": (), "targs": tuple(q), "matrix": m})
+        elif kind == 3:
+            ops.append({"op": "unitary", "ctrls": (), "targs": (q[0],), "matrix": synth.haar_unitary(rng, 2)})
+        else:
+            w = int(rng.integers(1, N + 1))
+            t = rng.permutation(N)[:w]
+            ops.append({"op": "gadget", "targs": tuple(int(x) for x in t),
+                        "paulis": tuple(int(x) for x in rng.integers(1, 4, size=w)), "theta": rng.uniform(-3, 3)})
+    psi = synth.random_state(rng, 1 << N)
+    circ = qs.Circuit(N, ops).compile(k, prec)
+    q = qs.Qureg(N, precision=prec).set_amps(psi)
+    circ.apply(q)
+    assert amp_err(q.get_amps(), oracle.run_ops(psi.copy(), ops)) < (1e-11 if prec == "c128" else 2e-5)
+
+
 def test_config5_fused_reduced(qs):
     """The 34-qubit generator at 14 qubits: 5-target gates with up to 4
     controls and heavy gadgets, fused with k = 6 in complex64."""
