@@ -204,6 +204,30 @@ def path_text(k):
     return f"tile steps of 2^{k} amplitudes: each step applies its operators on chip in one HBM pass"
 
 
+def bench_channels(q, torch, amp_bytes):
+    """One application of each bespoke channel on a density qureg: ms and
+    GB/s of the amplitudes it must read and write (dephasing touches half of
+    the Choi vector, two-qubit dephasing three quarters, the others all)."""
+    n = q.num_qubits
+    calls = [("dephasing", lambda: q.apply_dephasing(3, 0.1), 0.5),
+             ("dephasing_2q", lambda: q.apply_two_qubit_dephasing(2, n - 1, 0.1), 0.75),
+             ("depolarising", lambda: q.apply_depolarising(n - 1, 0.1), 1.0),
+             ("depolarising_2q", lambda: q.apply_two_qubit_depolarising(0, n - 2, 0.1), 1.0),
+             ("damping", lambda: q.apply_damping(5, 0.1), 1.0)]
+    res = {}
+    for name, fn, frac in calls:
+        fn()                                   # untimed first call
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(q.stream)
+        fn()
+        b.record(q.stream)
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        byts = 2 * amp_bytes * frac * (1 << (2 * n))
+        res[name] = {"ms": ms, "GBps": byts / (ms * 1e-3) / 1e9}
+    return res
+
+
 def bench_density(args, torch, qs, synth):
     """14-qubit density matrix (Choi vector of 2^28 amplitudes): 300 ops of
     Haar unitaries, depolarising, damping and random Kraus maps applied as
@@ -244,7 +268,8 @@ def bench_density(args, torch, qs, synth):
         ab = 16 if prec == "c128" else 8
         out[prec] = {"value": logical / step_s, "ms_per_step": step_s * 1e3,
                      "roofline": roofline(kinds, ab, 2 * n),
-                     "per_kind": per_kernel_table(kinds, ab)}
+                     "per_kind": per_kernel_table(kinds, ab),
+                     "channels": bench_channels(q, torch, ab)}
         if prec == "c128":
             # reference result of the plain FP64 path, from |0><0|, one application
             q.init_zero().run_ops(ops)

@@ -157,6 +157,33 @@ int qs_apply_superop(qs_qureg *q, const int *targs, int num_targs, const double 
 int qs_apply_kraus_map(qs_qureg *q, const int *targs, int num_targs,
                        const double *kraus, int num_ops);
 
+/*
+ * Decoherence channels on a density matrix, each one pass over the Choi
+ * vector with the channel's closed-form update (no superoperator):
+ *   dephasing, prob. p (Sec. "dephasing", Alg.
+ *     "distrib_dens_matr_one_qb_dephasing"): rho -> (1-p) rho + p Z rho Z,
+ *     i.e. beta_i -> (1 - 2p) beta_i where bits t and t+N of i differ; the
+ *     other half of the state is not touched;
+ *   two-qubit dephasing (Eq. "dephasing_2qb_update_rule", Alg.
+ *     "distrib_dens_matr_two_qb_dephasing"): Z on t1, t2 or both with total
+ *     prob. p; beta_i -> (1 - 4p/3) beta_i unless both principal pairs agree
+ *     (those three quarters only are read and written);
+ *   depolarising, total prob. p, p/3 per Pauli (Eq.
+ *     "depolarising_1qb_amp_update", Alg. "distrib_dens_matr_one_qb_depolarising");
+ *   two-qubit depolarising, total prob. p, p/15 per non-identity Pauli pair
+ *     (Eq. "2qb_depolarising_choi_amp_update", Alg.
+ *     "distrib_dens_matr_two_qb_depolarising");
+ *   amplitude damping, decay prob. p (Eq. "damping_amps_update", Alg.
+ *     "distrib_dens_matr_damping").
+ * 0 <= p <= 1 (QS_E_ARG otherwise); targets distinct and < N (QS_E_ARG);
+ * density matrices only (QS_E_PRECOND).  Asynchronous on the qureg's stream.
+ */
+int qs_apply_dephasing(qs_qureg *q, int target, double p);
+int qs_apply_two_qubit_dephasing(qs_qureg *q, int target1, int target2, double p);
+int qs_apply_depolarising(qs_qureg *q, int target, double p);
+int qs_apply_two_qubit_depolarising(qs_qureg *q, int target1, int target2, double p);
+int qs_apply_damping(qs_qureg *q, int target, double p);
+
 /* ---- calculations ---------------------------------------------------------- */
 
 /*

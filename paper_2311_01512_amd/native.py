@@ -63,6 +63,11 @@ _SIGS = {
     "qs_calc_trace": [_P, _PD, _PD],
     "qs_calc_purity": [_P, _PD, _PD],
     "qs_calc_inner_product": [_P, _P, _PD, _PD],
+    "qs_apply_dephasing": [_P, _I, _D],
+    "qs_apply_two_qubit_dephasing": [_P, _I, _I, _D],
+    "qs_apply_depolarising": [_P, _I, _D],
+    "qs_apply_two_qubit_depolarising": [_P, _I, _I, _D],
+    "qs_apply_damping": [_P, _I, _D],
     "qs_circuit_create": [_I, _PP],
     "qs_circuit_create_density": [_I, _PP],
     "qs_circuit_add_superop": [_P, _P, _I, _P],
@@ -204,6 +209,27 @@ def qs_apply_kraus_map(q, targs, kraus):
     if k.ndim != 3 or k.shape[1:] != (1 << t.size, 1 << t.size):
         raise ValueError(f"Kraus operators must have shape (M, {1 << t.size}, {1 << t.size})")
     check(lib.qs_apply_kraus_map(q, ptr(t), t.size, ptr(k.view(np.float64)), k.shape[0]), "qs_apply_kraus_map")
+
+
+def qs_apply_dephasing(q, target, p):
+    check(lib.qs_apply_dephasing(q, int(target), float(p)), "qs_apply_dephasing")
+
+
+def qs_apply_two_qubit_dephasing(q, target1, target2, p):
+    check(lib.qs_apply_two_qubit_dephasing(q, int(target1), int(target2), float(p)), "qs_apply_two_qubit_dephasing")
+
+
+def qs_apply_depolarising(q, target, p):
+    check(lib.qs_apply_depolarising(q, int(target), float(p)), "qs_apply_depolarising")
+
+
+def qs_apply_two_qubit_depolarising(q, target1, target2, p):
+    check(lib.qs_apply_two_qubit_depolarising(q, int(target1), int(target2), float(p)),
+          "qs_apply_two_qubit_depolarising")
+
+
+def qs_apply_damping(q, target, p):
+    check(lib.qs_apply_damping(q, int(target), float(p)), "qs_apply_damping")
 
 
 def qs_calc_partial_trace(q_in, targs, q_out):

@@ -107,6 +107,26 @@ class Qureg:
                 raise ValueError(f"unknown op {kind}")
         return self
 
+    def apply_dephasing(self, target, p):
+        N.qs_apply_dephasing(self._q, target, p)
+        return self
+
+    def apply_two_qubit_dephasing(self, target1, target2, p):
+        N.qs_apply_two_qubit_dephasing(self._q, target1, target2, p)
+        return self
+
+    def apply_depolarising(self, target, p):
+        N.qs_apply_depolarising(self._q, target, p)
+        return self
+
+    def apply_two_qubit_depolarising(self, target1, target2, p):
+        N.qs_apply_two_qubit_depolarising(self._q, target1, target2, p)
+        return self
+
+    def apply_damping(self, target, p):
+        N.qs_apply_damping(self._q, target, p)
+        return self
+
     # ---- calculations -----------------------------------------------------------------
     def partial_trace(self, targs, out=None):
         targs = list(targs)

@@ -9,7 +9,7 @@ from .circuits import (  # noqa: F401
     haar_unitary, haar_isometry, random_matrix, random_state,
     pauli_matrix_2x2, rotation_y, rotation_z,
     kraus_depolarising_1q, kraus_damping_1q, kraus_dephasing_1q,
-    kraus_depolarising_2q, kraus_random_isometry,
+    kraus_depolarising_2q, kraus_dephasing_2q, kraus_random_isometry,
     random_pauli_sum,
     config1_circuit, config2_circuit, config3_circuit, config4_batch,
     config5_circuit, op_qubits, count_logical_updates,

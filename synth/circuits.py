@@ -87,6 +87,14 @@ def kraus_dephasing_1q(p):
     return np.stack([np.sqrt(1 - p) * pauli_matrix_2x2(0), np.sqrt(p) * pauli_matrix_2x2(3)])
 
 
+def kraus_dephasing_2q(p):
+    """Z on the first, the second or both targets, each with weight p/3;
+    matrix index bit 0 is the first target."""
+    z, i2 = pauli_matrix_2x2(3), pauli_matrix_2x2(0)
+    return np.stack([np.sqrt(1 - p) * np.kron(i2, i2), np.sqrt(p / 3) * np.kron(i2, z),
+                     np.sqrt(p / 3) * np.kron(z, i2), np.sqrt(p / 3) * np.kron(z, z)])
+
+
 def kraus_depolarising_1q(p):
     ks = [np.sqrt(1 - p) * pauli_matrix_2x2(0)]
     ks += [np.sqrt(p / 3) * pauli_matrix_2x2(c) for c in (1, 2, 3)]

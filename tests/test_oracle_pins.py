@@ -224,6 +224,18 @@ def test_dephasing_rule():
     assert np.abs(got - want).max() < TOL
 
 
+def test_dephasing_2q_rule():
+    """Eq. dephasing_2qb_update_rule: unless both principal pairs agree, an
+    entry scales by 1 - 4p/3."""
+    rng = rng_for(16)
+    N, t1, t2, p = 3, 2, 0, 0.41
+    beta = D.choi(rand_dm(rng, N))
+    got = oracle.dm_apply_kraus(beta.copy(), [t1, t2], synth.kraus_dephasing_2q(p))
+    want = np.array([b if (_choi_bit(i, t1) == _choi_bit(i, t1 + N) and _choi_bit(i, t2) == _choi_bit(i, t2 + N))
+                     else (1 - 4 * p / 3) * b for i, b in enumerate(beta)])
+    assert np.abs(got - want).max() < TOL
+
+
 def test_depolarising_1q_rule():
     """Eq. depolarising_1qb_amp_update."""
     rng = rng_for(12)
