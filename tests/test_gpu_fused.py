@@ -211,3 +211,45 @@ def test_circuit_errors(qs):
         c.apply(q)                                   # compiled for the other precision
     with pytest.raises(ValueError):
         c.compile(7, "c64")
+
+
+def _random_mixed_ops(rng, N, count):
+    """Every operator shape the compilers handle: 1-4 target gates (dense,
+    diagonal, paired-sparse) with 0-4 controls, gadgets of any weight
+    including all-Z ones."""
+    ops = []
+    for _ in range(count):
+        kind = int(rng.integers(0, 6))
+        q = [int(x) for x in rng.permutation(N)]
+        if kind <= 2:
+            nt = int(rng.integers(1, 5))
+            nc = int(rng.integers(0, min(5, N - nt) + 1))
+            m = synth.haar_unitary(rng, 1 << nt)
+            if kind == 2 and nt <= 2:
+                s_ = int(rng.integers(0, 1 << nt))
+                m = m * np.array([[1 if (r ^ c) in (0, s_) else 0 for c in range(1 << nt)] for r in range(1 << nt)])
+            ops.append({"op": "unitary", "ctrls": tuple(q[nt:nt + nc]), "targs": tuple(q[:nt]), "matrix": m})
+        else:
+            w = int(rng.integers(1, N + 1))
+            codes = rng.integers(1, 4, size=w) if kind != 5 else np.full(w, 3)
+            ops.append({"op": "gadget", "targs": tuple(q[:w]), "paulis": tuple(int(c) for c in codes),
+                        "theta": rng.uniform(-3, 3)})
+    return ops
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_circuits_every_compile(qs, seed):
+    """Random circuits compiled plain, as dense blocks and as tile steps of
+    several widths, in both precisions, against the oracle."""
+    rng = np.random.default_rng(4000 + seed)
+    N = int(rng.integers(9, 13))
+    ops = _random_mixed_ops(rng, N, 120)
+    psi = synth.random_state(rng, 1 << N)
+    want = oracle.run_ops(psi.copy(), ops)
+    for prec in ("c128", "c64"):
+        for k in (0, 4, 8, 9, 10, 11, 12):
+            banner(f"random circuit seed={seed} N={N} k={k} {prec}")
+            circ = qs.Circuit(N, ops).compile(k, prec)
+            q = qs.Qureg(N, precision=prec).set_amps(psi)
+            circ.apply(q)
+            assert amp_err(q.get_amps(), want) < TOL[prec]
