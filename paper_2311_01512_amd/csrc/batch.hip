@@ -105,14 +105,14 @@ __device__ __forceinline__ uint64_t tile_offset(int j, const DStep &st)
     return o;
 }
 
-// 2 x 2 matrix of an operator; dir = -1 gives its adjoint.
+// 2 x 2 matrix of an operator; dir = -1 gives its adjoint.  A rotation's
+// cos and sin come from the per-operator table trig (filled by k_batch_trig
+// for the current parameters), not from a per-lane sincos.
 template <typename R>
-__device__ void op_matrix(const DOp &op, const double *params, int dir, C2<R> u[4])
+__device__ void op_matrix(const DOp &op, const double *trig, int dir, C2<R> u[4])
 {
     if (op.kind == BOP_ROT) {
-        const double ang = dir * op.scale * params[op.param];
-        double s, c;
-        sincos(ang, &s, &c);
+        const double c = trig[0], s = dir * trig[1];
         if (op.pauli == 1) {          // c 1 + i s X
             u[0] = mk<R>(c, 0); u[1] = mk<R>(0, s); u[2] = mk<R>(0, s); u[3] = mk<R>(c, 0);
         } else if (op.pauli == 2) {   // c 1 + i s Y
@@ -128,6 +128,19 @@ __device__ void op_matrix(const DOp &op, const double *params, int dir, C2<R> u[
         u[2] = mk<R>((R)op.m[2], (R)-op.m[3]);
         u[3] = mk<R>((R)op.m[6], (R)-op.m[7]);
     }
+}
+
+// cos and sin of every rotation's angle scale * parameter, once per run.
+__global__ __launch_bounds__(256) void k_batch_trig(const DOp *__restrict__ ops, int num_ops,
+                                                     const double *__restrict__ params, double *__restrict__ trig)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= num_ops) return;
+    const DOp op = ops[k];
+    double s = 0.0, c = 1.0;
+    if (op.kind == BOP_ROT) sincos(op.scale * params[op.param], &s, &c);
+    trig[2 * k] = c;
+    trig[2 * k + 1] = s;
 }
 
 template <typename R>
@@ -163,13 +176,13 @@ __device__ void tile_cz(C2<R> *v, int qn, const DOp &op, uint64_t base)
 }
 
 template <typename R>
-__device__ void tile_apply(C2<R> *v, int qn, const DOp &op, uint64_t base, const double *params, int dir)
+__device__ void tile_apply(C2<R> *v, int qn, const DOp &op, uint64_t base, const double *trig, int dir)
 {
     if (op.kind == BOP_CZ) {
         tile_cz<R>(v, qn, op, base);
     } else {
         C2<R> u[4];
-        op_matrix<R>(op, params, dir, u);
+        op_matrix<R>(op, trig, dir, u);
         tile_gate<R>(v, qn, op.pos0, u);
     }
 }
@@ -177,7 +190,7 @@ __device__ void tile_apply(C2<R> *v, int qn, const DOp &op, uint64_t base, const
 template <typename R>
 __global__ __launch_bounds__(256) void k_batch_forward(C2<R> *__restrict__ amps, const DStep *__restrict__ steps,
                                                         const DOp *__restrict__ ops, const uint2 *__restrict__ work,
-                                                        const double *__restrict__ params)
+                                                        const double *__restrict__ trig)
 {
     extern __shared__ unsigned char lds_raw[];
     C2<R> *v = reinterpret_cast<C2<R> *>(lds_raw);
@@ -189,7 +202,7 @@ __global__ __launch_bounds__(256) void k_batch_forward(C2<R> *__restrict__ amps,
     for (int j = threadIdx.x; j < T; j += blockDim.x) v[j] = a[base | tile_offset(j, st)];
     __syncthreads();
     for (int k = st.op_begin; k < st.op_end; k++) {
-        tile_apply<R>(v, st.qn, ops[k], base, params, +1);
+        tile_apply<R>(v, st.qn, ops[k], base, trig + 2 * k, +1);
         __syncthreads();
     }
     for (int j = threadIdx.x; j < T; j += blockDim.x) a[base | tile_offset(j, st)] = v[j];
@@ -197,15 +210,19 @@ __global__ __launch_bounds__(256) void k_batch_forward(C2<R> *__restrict__ amps,
 
 // Adjoint sweep over one tile of phi and lambda: for each operator, last
 // first, the rotation's partial <lambda|P|phi> over the tile, then
-// phi <- U^dagger phi and lambda <- U^dagger lambda.
+// phi <- U^dagger phi and lambda <- U^dagger lambda.  For a rotation both
+// happen in one pass over the pairs (j0, j1) it couples; each wavefront
+// reduces its share in FP64 and leaves it in LDS, and thread 0 adds the
+// wavefronts' shares (fixed order) after the barrier that ends the operator,
+// so a rotation costs no barrier of its own.
 template <typename R>
 __global__ __launch_bounds__(256) void k_batch_backward(C2<R> *__restrict__ amps, uint64_t lambda_base,
                                                          const DStep *__restrict__ steps, const DOp *__restrict__ ops,
                                                          const uint2 *__restrict__ work,
-                                                         const double *__restrict__ params, double *__restrict__ gpart)
+                                                         const double *__restrict__ trig, double *__restrict__ gpart)
 {
     extern __shared__ unsigned char lds_raw[];
-    __shared__ double red[32];
+    __shared__ double red[2][8];   // two rotations in flight, (re, im) of up to 4 wavefronts
     const uint2 w = work[blockIdx.x];
     const DStep &st = steps[w.x];
     const int T = 1 << st.qn;
@@ -214,50 +231,85 @@ __global__ __launch_bounds__(256) void k_batch_backward(C2<R> *__restrict__ amps
     const uint64_t base = insert_zeros(w.y, st.plan);
     C2<R> *a = amps + st.amp_off;
     C2<R> *l = amps + lambda_base + st.amp_off;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     for (int j = threadIdx.x; j < T; j += blockDim.x) {
         const uint64_t o = base | tile_offset(j, st);
         phi[j] = a[o];
         lam[j] = l[o];
     }
     __syncthreads();
+    uint64_t pend = ~0ULL;   // partial index of the rotation whose wave sums sit in red[pslot]
+    int pslot = 0;
+    auto flush = [&]() {
+        if (pend != ~0ULL && threadIdx.x == 0) {
+            double re = 0.0, im = 0.0;
+            for (int v = 0; v < nwaves; v++) {
+                re += red[pslot][2 * v];
+                im += red[pslot][2 * v + 1];
+            }
+            gpart[2 * pend] = re;
+            gpart[2 * pend + 1] = im;
+        }
+        pend = ~0ULL;
+    };
     for (int k = st.op_end - 1; k >= st.op_begin; k--) {
         const DOp &op = ops[k];
-        if (op.grad >= 0) {
-            double re = 0.0, im = 0.0;
-            const int pos = op.pos0;
-            for (int j = threadIdx.x; j < T; j += blockDim.x) {
-                const int bit = (j >> pos) & 1;
-                C2<R> p;   // (P phi)_j
-                if (op.pauli == 1) {
-                    p = phi[j ^ (1 << pos)];
-                } else if (op.pauli == 2) {
-                    const C2<R> x = phi[j ^ (1 << pos)];     // -i x if bit = 0, +i x if bit = 1
-                    p = bit ? mk<R>(-x.y, x.x) : mk<R>(x.y, -x.x);
-                } else {
-                    p = bit ? mk<R>(-phi[j].x, -phi[j].y) : phi[j];
-                }
-                const C2<R> y = lam[j];
-                re += (double)y.x * p.x + (double)y.y * p.y;
-                im += (double)y.x * p.y - (double)y.y * p.x;
-            }
-            bblock_sum2(re, im, red);
-            if (threadIdx.x == 0) {
-                gpart[2 * (op.gpart + w.y)] = re;
-                gpart[2 * (op.gpart + w.y) + 1] = im;
-            }
-            __syncthreads();
-        }
+        flush();   // the previous operator's barrier made its wave sums visible
         if (op.kind == BOP_CZ) {
             tile_cz<R>(phi, st.qn, op, base);
             tile_cz<R>(lam, st.qn, op, base);
         } else {
             C2<R> u[4];
-            op_matrix<R>(op, params, -1, u);
-            tile_gate<R>(phi, st.qn, op.pos0, u);
-            tile_gate<R>(lam, st.qn, op.pos0, u);
+            op_matrix<R>(op, trig + 2 * k, -1, u);
+            if (op.grad < 0) {
+                tile_gate<R>(phi, st.qn, op.pos0, u);
+                tile_gate<R>(lam, st.qn, op.pos0, u);
+            } else {
+                const int pos = op.pos0, lo = (1 << pos) - 1, np = T >> 1;
+                double re = 0.0, im = 0.0;
+                for (int p = threadIdx.x; p < np; p += blockDim.x) {
+                    const int j0 = (p & lo) | ((p & ~lo) << 1), j1 = j0 | (1 << pos);
+                    const C2<R> f0 = phi[j0], f1 = phi[j1], y0 = lam[j0], y1 = lam[j1];
+                    C2<R> p0, p1;   // (P phi) at j0 and j1
+                    if (op.pauli == 1) {
+                        p0 = f1;
+                        p1 = f0;
+                    } else if (op.pauli == 2) {   // Y: -i phi_j1 at j0, +i phi_j0 at j1
+                        p0 = mk<R>(f1.y, -f1.x);
+                        p1 = mk<R>(-f0.y, f0.x);
+                    } else {
+                        p0 = f0;
+                        p1 = mk<R>(-f1.x, -f1.y);
+                    }
+                    re += (double)y0.x * p0.x + (double)y0.y * p0.y + (double)y1.x * p1.x + (double)y1.y * p1.y;
+                    im += (double)y0.x * p0.y - (double)y0.y * p0.x + (double)y1.x * p1.y - (double)y1.y * p1.x;
+                    C2<R> g0 = mk<R>(0, 0), g1 = mk<R>(0, 0), h0 = mk<R>(0, 0), h1 = mk<R>(0, 0);
+                    cmac<R>(g0, u[0], f0);
+                    cmac<R>(g0, u[1], f1);
+                    cmac<R>(g1, u[2], f0);
+                    cmac<R>(g1, u[3], f1);
+                    cmac<R>(h0, u[0], y0);
+                    cmac<R>(h0, u[1], y1);
+                    cmac<R>(h1, u[2], y0);
+                    cmac<R>(h1, u[3], y1);
+                    phi[j0] = g0;
+                    phi[j1] = g1;
+                    lam[j0] = h0;
+                    lam[j1] = h1;
+                }
+                re = bwave_sum(re);
+                im = bwave_sum(im);
+                pslot = k & 1;
+                if (lane == 0) {
+                    red[pslot][2 * wave] = re;
+                    red[pslot][2 * wave + 1] = im;
+                }
+                pend = op.gpart + w.y;
+            }
         }
         __syncthreads();
     }
+    flush();
     for (int j = threadIdx.x; j < T; j += blockDim.x) {
         const uint64_t o = base | tile_offset(j, st);
         a[o] = phi[j];
@@ -382,6 +434,8 @@ struct qs_batch {
     std::vector<int> rot_param;      // global parameter of each rotation slot
     std::vector<double> rot_scale;
     double *d_params = nullptr, *h_params = nullptr;
+    double *d_trig = nullptr;   // cos, sin of every operator's angle
+    int num_ops = 0;
     int total_params = 0;
     hipGraphExec_t g_fwd = nullptr, g_full = nullptr;
     hipGraph_t gr_fwd = nullptr, gr_full = nullptr;
@@ -443,6 +497,9 @@ static int launch_phase_kernels(qs_batch *b, bool grads)
     const size_t ab = b->precision == QS_C64 ? 8 : 16;
     const size_t lds1 = ((size_t)1 << b->tile_qubits) * ab;
     const int P = (int)b->d_work.size();
+    hipLaunchKernelGGL(k_batch_trig, dim3((unsigned)((b->num_ops + 255) / 256)), dim3(256), 0, b->stream,
+                       (const DOp *)b->d_ops, b->num_ops, (const double *)b->d_params, b->d_trig);
+    QS_LAUNCH_CHECK();
     // initial states
     if (b->precision == QS_C64)
         hipLaunchKernelGGL(k_batch_init<float>, dim3(b->amp_blocks), dim3(256), 0, b->stream, (float2 *)b->amps,
@@ -456,11 +513,11 @@ static int launch_phase_kernels(qs_batch *b, bool grads)
         if (b->precision == QS_C64)
             hipLaunchKernelGGL(k_batch_forward<float>, dim3(b->phase_blocks[p]), dim3(256), lds1, b->stream,
                                (float2 *)b->amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
-                               (const uint2 *)b->d_work[p], (const double *)b->d_params);
+                               (const uint2 *)b->d_work[p], (const double *)b->d_trig);
         else
             hipLaunchKernelGGL(k_batch_forward<double>, dim3(b->phase_blocks[p]), dim3(256), lds1, b->stream,
                                (double2 *)b->amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
-                               (const uint2 *)b->d_work[p], (const double *)b->d_params);
+                               (const uint2 *)b->d_work[p], (const double *)b->d_trig);
         QS_LAUNCH_CHECK();
     }
     const BlockMap bm{b->d_bm_circ, b->d_bm_start};
@@ -482,11 +539,11 @@ static int launch_phase_kernels(qs_batch *b, bool grads)
         if (b->precision == QS_C64)
             hipLaunchKernelGGL(k_batch_backward<float>, dim3(b->phase_blocks[p]), dim3(256), 2 * lds1, b->stream,
                                (float2 *)b->amps, b->total_amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
-                               (const uint2 *)b->d_work[p], (const double *)b->d_params, b->d_gpart);
+                               (const uint2 *)b->d_work[p], (const double *)b->d_trig, b->d_gpart);
         else
             hipLaunchKernelGGL(k_batch_backward<double>, dim3(b->phase_blocks[p]), dim3(256), 2 * lds1, b->stream,
                                (double2 *)b->amps, b->total_amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
-                               (const uint2 *)b->d_work[p], (const double *)b->d_params, b->d_gpart);
+                               (const uint2 *)b->d_work[p], (const double *)b->d_trig, b->d_gpart);
         QS_LAUNCH_CHECK();
     }
     if (b->num_rot > 0) {
@@ -554,6 +611,7 @@ static void release(qs_batch *b)
     f(b->d_gop);
     f(b->d_gfirst);
     f(b->d_params);
+    f(b->d_trig);
     if (b->h_energy) (void)hipHostFree(b->h_energy);
     if (b->h_gop) (void)hipHostFree(b->h_gop);
     if (b->h_params) (void)hipHostFree(b->h_params);
@@ -571,6 +629,7 @@ static void release(qs_batch *b)
     b->d_gpart = b->d_gop = b->h_gop = nullptr;
     b->d_gfirst = nullptr;
     b->d_params = b->h_params = nullptr;
+    b->d_trig = nullptr;
     b->compiled = false;
 }
 
@@ -860,6 +919,8 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
     if ((rc = upload(&b->d_gpart, nullptr, sizeof(double) * 2 * gfirst.back())) != QS_OK) return rc;
     if ((rc = upload(&b->d_gop, nullptr, sizeof(double) * 2 * std::max(1, b->num_rot))) != QS_OK) return rc;
     if ((rc = upload(&b->d_params, nullptr, sizeof(double) * std::max(1, b->total_params))) != QS_OK) return rc;
+    b->num_ops = (int)ops.size();
+    if ((rc = upload(&b->d_trig, nullptr, sizeof(double) * 2 * std::max(1, b->num_ops))) != QS_OK) return rc;
     if (hipHostMalloc(&b->h_energy, sizeof(double) * 2 * b->circs.size(), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&b->h_gop, sizeof(double) * 2 * std::max(1, b->num_rot), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&b->h_params, sizeof(double) * std::max(1, b->total_params), hipHostMallocDefault) != hipSuccess) {
