@@ -51,6 +51,8 @@ struct DOp {
     int param;        // global parameter index (rotations)
     int grad;         // rotation slot, -1 for other operators
     uint64_t gpart;   // first gradient partial of this rotation (one per tile)
+    int rbit;         // register bit of a 1-qubit operator in its phase (register path)
+    int slot;         // gradient slot of a rotation within its phase (register path)
     double scale;
     double m[8];      // fixed gate, row-major (re, im)
 };
@@ -60,6 +62,22 @@ struct DStep {
     InsertPlan plan;  // zeros at the step's qubits: spreads the tile number
     int qn;
     int qpos[kTileMax];
+    int op_begin, op_end;
+    int ph_begin, ph_end;   // register phases (steps of >= kRegMinQubits qubits)
+};
+
+// Register phases of a step (tiles of at least 2^kRegMinQubits amplitudes):
+// thread t of the block holds the 8 tile coordinates tau(t) | rho(u), where
+// rho puts the bits of u on the coordinates rc[0..2] and tau deposits the
+// bits of t, in order, on the others (zeros inserted at lo).  Every 1-qubit
+// operator of the phase acts on one of the rc coordinates, so it only mixes
+// registers of one thread; CZ is diagonal and needs none.  The tile moves
+// through LDS once per phase change.
+constexpr int kRegMinQubits = 9;     // 64 threads: whole wavefronts
+constexpr int kPhaseRotMax = 32;     // gradient slots per phase
+struct BPhase {
+    uint32_t lo[3];                  // (1 << rc) - 1, ascending
+    int rc[3];                       // coordinate of register bit j
     int op_begin, op_end;
 };
 
@@ -109,7 +127,7 @@ __device__ __forceinline__ uint64_t tile_offset(int j, const DStep &st)
 // cos and sin come from the per-operator table trig (filled by k_batch_trig
 // for the current parameters), not from a per-lane sincos.
 template <typename R>
-__device__ void op_matrix(const DOp &op, const double *trig, int dir, C2<R> u[4])
+__device__ __forceinline__ void op_matrix(const DOp &op, const double *trig, int dir, C2<R> (&u)[4])
 {
     if (op.kind == BOP_ROT) {
         const double c = trig[0], s = dir * trig[1];
@@ -121,6 +139,7 @@ __device__ void op_matrix(const DOp &op, const double *trig, int dir, C2<R> u[4]
             u[0] = mk<R>(c, s); u[1] = mk<R>(0, 0); u[2] = mk<R>(0, 0); u[3] = mk<R>(c, -s);
         }
     } else if (dir > 0) {
+#pragma unroll
         for (int k = 0; k < 4; k++) u[k] = mk<R>((R)op.m[2 * k], (R)op.m[2 * k + 1]);
     } else {                          // conjugate transpose
         u[0] = mk<R>((R)op.m[0], (R)-op.m[1]);
@@ -144,7 +163,7 @@ __global__ __launch_bounds__(256) void k_batch_trig(const DOp *__restrict__ ops,
 }
 
 template <typename R>
-__device__ void tile_gate(C2<R> *v, int qn, int pos, const C2<R> u[4])
+__device__ void tile_gate(C2<R> *v, int qn, int pos, const C2<R> (&u)[4])
 {
     const int np = 1 << (qn - 1);
     const int lo = (1 << pos) - 1;
@@ -317,6 +336,313 @@ __global__ __launch_bounds__(256) void k_batch_backward(C2<R> *__restrict__ amps
     }
 }
 
+// ---- register-phase path (tiles of >= 2^kRegMinQubits amplitudes) ----------------------
+
+__device__ __forceinline__ uint32_t bphase_tau(uint32_t t, const BPhase &ph)
+{
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        const uint32_t lo = ph.lo[b];
+        t = (t & lo) | ((t & ~lo) << 1);
+    }
+    return t;
+}
+
+__device__ __forceinline__ uint32_t bphase_rho(int u, const BPhase &ph)
+{
+    return ((uint32_t)(u & 1) << ph.rc[0]) | ((uint32_t)((u >> 1) & 1) << ph.rc[1]) |
+           ((uint32_t)((u >> 2) & 1) << ph.rc[2]);
+}
+
+// 2 x 2 matrix (m0 m1; m2 m3) on the register pairs (u0, u0 | 1 << J).
+template <typename R, int J>
+__device__ __forceinline__ void reg_pairs(C2<R> (&x)[8], C2<R> m0, C2<R> m1, C2<R> m2, C2<R> m3)
+{
+#pragma unroll
+    for (int u0 = 0; u0 < 8; u0++) {
+        if ((u0 >> J) & 1) continue;
+        const C2<R> a = x[u0], b = x[u0 | (1 << J)];
+        C2<R> p = mk<R>(0, 0), q = mk<R>(0, 0);
+        cmac<R>(p, m0, a);
+        cmac<R>(p, m1, b);
+        cmac<R>(q, m2, a);
+        cmac<R>(q, m3, b);
+        x[u0] = p;
+        x[u0 | (1 << J)] = q;
+    }
+    // a distinct empty statement per J: keeps the compiler from sinking the
+    // three dispatch arms of reg_gate into one, which would address the
+    // registers through pointers (private memory)
+    if constexpr (J == 0) asm volatile("; reg pairs 0");
+    else if constexpr (J == 1) asm volatile("; reg pairs 1");
+    else asm volatile("; reg pairs 2");
+}
+
+// Partial of <lambda|P|phi> over the register pairs (u0, u0 | 1 << J) of a
+// rotation exp(i theta P) on register bit J.
+template <typename R, int J>
+__device__ __forceinline__ void reg_grad_pairs(const C2<R> (&x)[8], const C2<R> (&y)[8], int pauli, double &re,
+                                               double &im)
+{
+#pragma unroll
+    for (int u0 = 0; u0 < 8; u0++) {
+        if ((u0 >> J) & 1) continue;
+        const int u1 = u0 | (1 << J);
+        const C2<R> f0 = x[u0], f1 = x[u1], l0 = y[u0], l1 = y[u1];
+        C2<R> p0, p1;   // (P phi) at the two members
+        if (pauli == 1) {
+            p0 = f1;
+            p1 = f0;
+        } else if (pauli == 2) {   // Y: -i phi_1 at member 0, +i phi_0 at member 1
+            p0 = mk<R>(f1.y, -f1.x);
+            p1 = mk<R>(-f0.y, f0.x);
+        } else {
+            p0 = f0;
+            p1 = mk<R>(-f1.x, -f1.y);
+        }
+        re += (double)l0.x * p0.x + (double)l0.y * p0.y + (double)l1.x * p1.x + (double)l1.y * p1.y;
+        im += (double)l0.x * p0.y - (double)l0.y * p0.x + (double)l1.x * p1.y - (double)l1.y * p1.x;
+    }
+    if constexpr (J == 0) asm volatile("; grad pairs 0");
+    else if constexpr (J == 1) asm volatile("; grad pairs 1");
+    else asm volatile("; grad pairs 2");
+}
+
+template <typename R>
+__device__ __forceinline__ void reg_gate(C2<R> (&x)[8], int rbit, const C2<R> (&u)[4])
+{
+    switch (rbit) {
+    case 0: reg_pairs<R, 0>(x, u[0], u[1], u[2], u[3]); break;
+    case 1: reg_pairs<R, 1>(x, u[0], u[1], u[2], u[3]); break;
+    default: reg_pairs<R, 2>(x, u[0], u[1], u[2], u[3]); break;
+    }
+}
+
+// CZ: sign flip where both qubits are 1 (a qubit outside the tile reads the
+// tile's base bit).
+template <typename R>
+__device__ __forceinline__ void reg_cz(C2<R> (&x)[8], const DOp &op, uint32_t tau, const BPhase &ph, uint64_t base)
+{
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const uint32_t c = tau | bphase_rho(u, ph);
+        const uint32_t b0 = op.pos0 >= 0 ? (c >> op.pos0) & 1u : (uint32_t)((base >> op.q0) & 1ULL);
+        const uint32_t b1 = op.pos1 >= 0 ? (c >> op.pos1) & 1u : (uint32_t)((base >> op.q1) & 1ULL);
+        if (b0 & b1) x[u] = mk<R>(-x[u].x, -x[u].y);
+    }
+}
+
+// Global offset of tile coordinates c (deposited at the step's qubits).
+__device__ __forceinline__ uint64_t tile_offset_bits(uint32_t c, const DStep &st)
+{
+    uint64_t o = 0;
+    for (int b = 0; b < st.qn; b++) o |= (uint64_t)((c >> b) & 1u) << st.qpos[b];
+    return o;
+}
+
+// Global offsets of the 8 registers of a phase: the qubits of rc[j] for the
+// bits j of u (no loops, so register indices stay compile-time).
+struct RegOffsets {
+    uint64_t q[3];
+    __device__ __forceinline__ RegOffsets(const BPhase &ph, const DStep &st)
+    {
+#pragma unroll
+        for (int j = 0; j < 3; j++) q[j] = 1ULL << st.qpos[ph.rc[j]];
+    }
+    __device__ __forceinline__ uint64_t operator()(int u) const
+    {
+        return ((u & 1) ? q[0] : 0ULL) | ((u & 2) ? q[1] : 0ULL) | ((u & 4) ? q[2] : 0ULL);
+    }
+};
+
+template <typename R>
+__global__ __launch_bounds__(512) void k_batch_forward_reg(C2<R> *__restrict__ amps, const DStep *__restrict__ steps,
+                                                            const BPhase *__restrict__ phases,
+                                                            const DOp *__restrict__ ops, const uint2 *__restrict__ work,
+                                                            const double *__restrict__ trig)
+{
+    extern __shared__ unsigned char lds_raw[];
+    C2<R> *v = reinterpret_cast<C2<R> *>(lds_raw);
+    const uint2 w = work[blockIdx.x];
+    const DStep &st = steps[w.x];
+    const uint64_t base = insert_zeros(w.y, st.plan);
+    C2<R> *a = amps + st.amp_off;
+    const uint32_t t = threadIdx.x;
+    const bool active = t < (1u << (st.qn - 3));   // whole wavefronts (qn >= 9)
+    const BPhase &f = phases[st.ph_begin];
+    uint32_t tau = bphase_tau(t, f);
+    C2<R> x[8];
+    if (active) {
+        const uint64_t xo = base | tile_offset_bits(tau, st);
+        const RegOffsets ro(f, st);
+#pragma unroll
+        for (int u = 0; u < 8; u++) x[u] = a[xo | ro(u)];
+    }
+    for (int p = st.ph_begin; p < st.ph_end; p++) {
+        const BPhase &P = phases[p];
+        if (p > st.ph_begin) {
+            const BPhase &Q = phases[p - 1];
+            const uint32_t tn = bphase_tau(t, P);
+            __syncthreads();   // earlier reads of the LDS tile are done
+            if (active) {
+#pragma unroll
+                for (int u = 0; u < 8; u++) v[tau | bphase_rho(u, Q)] = x[u];
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int u = 0; u < 8; u++) x[u] = v[tn | bphase_rho(u, P)];
+            }
+            tau = tn;
+        }
+        if (!active) continue;
+        for (int k = P.op_begin; k < P.op_end; k++) {
+            const DOp &op = ops[k];
+            if (op.kind == BOP_CZ) {
+                reg_cz<R>(x, op, tau, P, base);
+            } else {
+                C2<R> u[4];
+                op_matrix<R>(op, trig + 2 * k, +1, u);
+                reg_gate<R>(x, op.rbit, u);
+            }
+        }
+    }
+    if (active) {
+        const uint64_t xo = base | tile_offset_bits(tau, st);
+        const RegOffsets ro(phases[st.ph_end - 1], st);
+#pragma unroll
+        for (int u = 0; u < 8; u++) a[xo | ro(u)] = x[u];
+    }
+}
+
+// Adjoint sweep on registers: phases and operators last first; a rotation's
+// partial <lambda|P|phi> comes from the register pairs it couples, before
+// U^dagger is applied to both states.  Each wavefront leaves its partial in
+// the rotation's LDS slot; thread 0 adds the wavefronts' partials (fixed
+// order) after the next barrier.
+template <typename R>
+__global__ __launch_bounds__(512) void k_batch_backward_reg(C2<R> *__restrict__ amps, uint64_t lambda_base,
+                                                             const DStep *__restrict__ steps,
+                                                             const BPhase *__restrict__ phases,
+                                                             const DOp *__restrict__ ops,
+                                                             const uint2 *__restrict__ work,
+                                                             const double *__restrict__ trig,
+                                                             double *__restrict__ gpart)
+{
+    extern __shared__ unsigned char lds_raw[];
+    __shared__ double red[kPhaseRotMax][8][2];
+    const uint2 w = work[blockIdx.x];
+    const DStep &st = steps[w.x];
+    const uint64_t base = insert_zeros(w.y, st.plan);
+    const int T = 1 << st.qn;
+    C2<R> *vphi = reinterpret_cast<C2<R> *>(lds_raw);
+    C2<R> *vlam = vphi + T;
+    C2<R> *a = amps + st.amp_off;
+    C2<R> *l = amps + lambda_base + st.amp_off;
+    const uint32_t t = threadIdx.x;
+    const uint32_t nthr = 1u << (st.qn - 3);
+    const bool active = t < nthr;
+    const int lane = t & 63, wave = t >> 6, nwaves = (int)(nthr >> 6);
+    const BPhase &f = phases[st.ph_end - 1];
+    uint32_t tau = bphase_tau(t, f);
+    C2<R> x[8], y[8];
+    if (active) {
+        const uint64_t xo = base | tile_offset_bits(tau, st);
+        const RegOffsets ro(f, st);
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const uint64_t o = xo | ro(u);
+            x[u] = a[o];
+            y[u] = l[o];
+        }
+    }
+    int pend_phase = -1;   // phase whose rotation partials sit in red
+    auto flush = [&]() {
+        if (pend_phase >= 0 && t == 0) {
+            const BPhase &D = phases[pend_phase];
+            for (int k = D.op_begin; k < D.op_end; k++) {
+                const DOp &op = ops[k];
+                if (op.grad < 0) continue;
+                double re = 0.0, im = 0.0;
+                for (int v2 = 0; v2 < nwaves; v2++) {
+                    re += red[op.slot][v2][0];
+                    im += red[op.slot][v2][1];
+                }
+                gpart[2 * (op.gpart + w.y)] = re;
+                gpart[2 * (op.gpart + w.y) + 1] = im;
+            }
+        }
+        pend_phase = -1;
+    };
+    for (int p = st.ph_end - 1; p >= st.ph_begin; p--) {
+        const BPhase &P = phases[p];
+        if (p < st.ph_end - 1) {
+            const BPhase &Q = phases[p + 1];
+            const uint32_t tn = bphase_tau(t, P);
+            __syncthreads();   // earlier LDS reads done; the finished phase's partials visible
+            flush();
+            if (active) {
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const uint32_t c = tau | bphase_rho(u, Q);
+                    vphi[c] = x[u];
+                    vlam[c] = y[u];
+                }
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const uint32_t c = tn | bphase_rho(u, P);
+                    x[u] = vphi[c];
+                    y[u] = vlam[c];
+                }
+            }
+            tau = tn;
+        }
+        if (!active) continue;
+        for (int k = P.op_end - 1; k >= P.op_begin; k--) {
+            const DOp &op = ops[k];
+            if (op.kind == BOP_CZ) {
+                reg_cz<R>(x, op, tau, P, base);
+                reg_cz<R>(y, op, tau, P, base);
+                continue;
+            }
+            C2<R> u[4];
+            op_matrix<R>(op, trig + 2 * k, -1, u);
+            if (op.grad >= 0) {
+                double re = 0.0, im = 0.0;
+                switch (op.rbit) {
+                case 0: reg_grad_pairs<R, 0>(x, y, op.pauli, re, im); break;
+                case 1: reg_grad_pairs<R, 1>(x, y, op.pauli, re, im); break;
+                default: reg_grad_pairs<R, 2>(x, y, op.pauli, re, im); break;
+                }
+                re = bwave_sum(re);
+                im = bwave_sum(im);
+                if (lane == 0) {
+                    red[op.slot][wave][0] = re;
+                    red[op.slot][wave][1] = im;
+                }
+            }
+            reg_gate<R>(x, op.rbit, u);
+            reg_gate<R>(y, op.rbit, u);
+        }
+        pend_phase = p;
+    }
+    __syncthreads();
+    flush();
+    if (active) {
+        const uint64_t xo = base | tile_offset_bits(tau, st);
+        const RegOffsets ro(phases[st.ph_begin], st);
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const uint64_t o = xo | ro(u);
+            a[o] = x[u];
+            l[o] = y[u];
+        }
+    }
+}
+
 // Per-block circuit table of the flat amplitude range.
 struct BlockMap {
     const int *circ;         // circuit of each 256-amplitude block
@@ -435,6 +761,9 @@ struct qs_batch {
     std::vector<double> rot_scale;
     double *d_params = nullptr, *h_params = nullptr;
     double *d_trig = nullptr;   // cos, sin of every operator's angle
+    std::vector<uint2 *> d_work_reg;          // register-path work lists per launch step
+    std::vector<unsigned> phase_blocks_reg;
+    BPhase *d_phases = nullptr;
     int num_ops = 0;
     int total_params = 0;
     hipGraphExec_t g_fwd = nullptr, g_full = nullptr;
@@ -468,6 +797,9 @@ static void plan_circuit(BCirc &c, int TQ, int C)
                 if (c.ops[k].kind == BOP_CZ) continue;   // diagonal: needs no tile qubit
                 Q |= s;
             }
+            // fill the step to TQ qubits with the lowest free ones (longer
+            // contiguous runs, and tiles the register path takes)
+            for (int q = C; q < c.n && __builtin_popcountll(Q) < TQ; q++) Q |= 1ULL << q;
         }
         BStep st;
         st.qmask = Q;
@@ -508,17 +840,32 @@ static int launch_phase_kernels(qs_batch *b, bool grads)
         hipLaunchKernelGGL(k_batch_init<double>, dim3(b->amp_blocks), dim3(256), 0, b->stream, (double2 *)b->amps,
                            BlockMap{b->d_bm_circ, b->d_bm_start}, (const uint64_t *)b->d_offs, (const int *)b->d_nq);
     QS_LAUNCH_CHECK();
+    const unsigned rblock = 1u << (b->tile_qubits - 3);   // register path: 8 amplitudes per thread
     for (int p = 0; p < P; p++) {
-        if (b->phase_blocks[p] == 0) continue;
-        if (b->precision == QS_C64)
-            hipLaunchKernelGGL(k_batch_forward<float>, dim3(b->phase_blocks[p]), dim3(256), lds1, b->stream,
-                               (float2 *)b->amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
-                               (const uint2 *)b->d_work[p], (const double *)b->d_trig);
-        else
-            hipLaunchKernelGGL(k_batch_forward<double>, dim3(b->phase_blocks[p]), dim3(256), lds1, b->stream,
-                               (double2 *)b->amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
-                               (const uint2 *)b->d_work[p], (const double *)b->d_trig);
-        QS_LAUNCH_CHECK();
+        if (b->phase_blocks[p] > 0) {
+            if (b->precision == QS_C64)
+                hipLaunchKernelGGL(k_batch_forward<float>, dim3(b->phase_blocks[p]), dim3(256), lds1, b->stream,
+                                   (float2 *)b->amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
+                                   (const uint2 *)b->d_work[p], (const double *)b->d_trig);
+            else
+                hipLaunchKernelGGL(k_batch_forward<double>, dim3(b->phase_blocks[p]), dim3(256), lds1, b->stream,
+                                   (double2 *)b->amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
+                                   (const uint2 *)b->d_work[p], (const double *)b->d_trig);
+            QS_LAUNCH_CHECK();
+        }
+        if (b->phase_blocks_reg[p] > 0) {
+            if (b->precision == QS_C64)
+                hipLaunchKernelGGL(k_batch_forward_reg<float>, dim3(b->phase_blocks_reg[p]), dim3(rblock), lds1,
+                                   b->stream, (float2 *)b->amps, (const DStep *)b->d_steps,
+                                   (const BPhase *)b->d_phases, (const DOp *)b->d_ops,
+                                   (const uint2 *)b->d_work_reg[p], (const double *)b->d_trig);
+            else
+                hipLaunchKernelGGL(k_batch_forward_reg<double>, dim3(b->phase_blocks_reg[p]), dim3(rblock), lds1,
+                                   b->stream, (double2 *)b->amps, (const DStep *)b->d_steps,
+                                   (const BPhase *)b->d_phases, (const DOp *)b->d_ops,
+                                   (const uint2 *)b->d_work_reg[p], (const double *)b->d_trig);
+            QS_LAUNCH_CHECK();
+        }
     }
     const BlockMap bm{b->d_bm_circ, b->d_bm_start};
     if (b->precision == QS_C64)
@@ -535,16 +882,32 @@ static int launch_phase_kernels(qs_batch *b, bool grads)
     QS_LAUNCH_CHECK();
     if (!grads) return QS_OK;
     for (int p = P - 1; p >= 0; p--) {
-        if (b->phase_blocks[p] == 0) continue;
-        if (b->precision == QS_C64)
-            hipLaunchKernelGGL(k_batch_backward<float>, dim3(b->phase_blocks[p]), dim3(256), 2 * lds1, b->stream,
-                               (float2 *)b->amps, b->total_amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
-                               (const uint2 *)b->d_work[p], (const double *)b->d_trig, b->d_gpart);
-        else
-            hipLaunchKernelGGL(k_batch_backward<double>, dim3(b->phase_blocks[p]), dim3(256), 2 * lds1, b->stream,
-                               (double2 *)b->amps, b->total_amps, (const DStep *)b->d_steps, (const DOp *)b->d_ops,
-                               (const uint2 *)b->d_work[p], (const double *)b->d_trig, b->d_gpart);
-        QS_LAUNCH_CHECK();
+        if (b->phase_blocks[p] > 0) {
+            if (b->precision == QS_C64)
+                hipLaunchKernelGGL(k_batch_backward<float>, dim3(b->phase_blocks[p]), dim3(256), 2 * lds1,
+                                   b->stream, (float2 *)b->amps, b->total_amps, (const DStep *)b->d_steps,
+                                   (const DOp *)b->d_ops, (const uint2 *)b->d_work[p], (const double *)b->d_trig,
+                                   b->d_gpart);
+            else
+                hipLaunchKernelGGL(k_batch_backward<double>, dim3(b->phase_blocks[p]), dim3(256), 2 * lds1,
+                                   b->stream, (double2 *)b->amps, b->total_amps, (const DStep *)b->d_steps,
+                                   (const DOp *)b->d_ops, (const uint2 *)b->d_work[p], (const double *)b->d_trig,
+                                   b->d_gpart);
+            QS_LAUNCH_CHECK();
+        }
+        if (b->phase_blocks_reg[p] > 0) {
+            if (b->precision == QS_C64)
+                hipLaunchKernelGGL(k_batch_backward_reg<float>, dim3(b->phase_blocks_reg[p]), dim3(rblock),
+                                   2 * lds1, b->stream, (float2 *)b->amps, b->total_amps,
+                                   (const DStep *)b->d_steps, (const BPhase *)b->d_phases, (const DOp *)b->d_ops,
+                                   (const uint2 *)b->d_work_reg[p], (const double *)b->d_trig, b->d_gpart);
+            else
+                hipLaunchKernelGGL(k_batch_backward_reg<double>, dim3(b->phase_blocks_reg[p]), dim3(rblock),
+                                   2 * lds1, b->stream, (double2 *)b->amps, b->total_amps,
+                                   (const DStep *)b->d_steps, (const BPhase *)b->d_phases, (const DOp *)b->d_ops,
+                                   (const uint2 *)b->d_work_reg[p], (const double *)b->d_trig, b->d_gpart);
+            QS_LAUNCH_CHECK();
+        }
     }
     if (b->num_rot > 0) {
         hipLaunchKernelGGL(k_batch_grad, dim3((b->num_rot + 255) / 256), dim3(256), 0, b->stream,
@@ -598,6 +961,12 @@ static void release(qs_batch *b)
     f(b->d_ops);
     for (auto *w : b->d_work) f(w);
     b->d_work.clear();
+    b->phase_blocks.clear();
+    for (auto *w : b->d_work_reg) f(w);
+    b->d_work_reg.clear();
+    b->phase_blocks_reg.clear();
+    f(b->d_phases);
+    b->d_phases = nullptr;
     f(b->d_bm_circ);
     f(b->d_bm_start);
     f(b->d_offs);
@@ -789,6 +1158,7 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
     // steps, operators, rotation slots and gradient partials
     std::vector<DStep> steps;
     std::vector<DOp> ops;
+    std::vector<BPhase> phases;
     std::vector<uint64_t> gfirst{0};
     b->rot_param.clear();
     b->rot_scale.clear();
@@ -836,20 +1206,56 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
                 ops.push_back(x);
             }
             d.op_end = (int)ops.size();
+            d.ph_begin = d.ph_end = (int)phases.size();
+            if (d.qn >= kRegMinQubits) {
+                // register phases: at most 3 operator coordinates and
+                // kPhaseRotMax rotations each, operators kept in order
+                int k = d.op_begin;
+                while (k < d.op_end) {
+                    BPhase ph{};
+                    std::vector<int> R;
+                    int nrot = 0;
+                    ph.op_begin = k;
+                    for (; k < d.op_end; k++) {
+                        DOp &x = ops[k];
+                        if (x.kind == BOP_CZ) continue;
+                        const bool in = std::find(R.begin(), R.end(), x.pos0) != R.end();
+                        if (!in && R.size() == 3) break;
+                        if (x.kind == BOP_ROT && nrot == kPhaseRotMax) break;
+                        if (!in) R.push_back(x.pos0);
+                        if (x.kind == BOP_ROT) x.slot = nrot++;
+                    }
+                    ph.op_end = k;
+                    for (int cc = d.qn - 1; R.size() < 3; cc--)
+                        if (std::find(R.begin(), R.end(), cc) == R.end()) R.push_back(cc);
+                    std::vector<int> sorted_r = R;
+                    std::sort(sorted_r.begin(), sorted_r.end());
+                    for (int j = 0; j < 3; j++) {
+                        ph.rc[j] = R[j];
+                        ph.lo[j] = (1u << sorted_r[j]) - 1u;
+                    }
+                    for (int kk = ph.op_begin; kk < ph.op_end; kk++)
+                        if (ops[kk].kind != BOP_CZ)
+                            ops[kk].rbit = (int)(std::find(R.begin(), R.end(), ops[kk].pos0) - R.begin());
+                    phases.push_back(ph);
+                }
+                d.ph_end = (int)phases.size();
+            }
             step_index[ci].push_back((int)steps.size());
             steps.push_back(d);
         }
     }
     b->num_rot = (int)b->rot_param.size();
 
-    // per-phase work lists: (step, tile) per block
-    std::vector<std::vector<uint2>> work(max_steps);
+    // per-phase work lists: (step, tile) per block, register path or LDS path
+    std::vector<std::vector<uint2>> work(max_steps), work_reg(max_steps);
     for (size_t ci = 0; ci < b->circs.size(); ci++) {
         const BCirc &c = b->circs[ci];
         for (size_t s = 0; s < c.steps.size(); s++) {
             const int si = step_index[ci][s];
             const uint64_t tiles = 1ULL << (c.n - steps[si].qn);
-            for (uint64_t t = 0; t < tiles; t++) work[s].push_back(make_uint2((unsigned)si, (unsigned)t));
+            auto &wl = steps[si].qn >= kRegMinQubits ? work_reg[s] : work[s];
+            for (uint64_t t = 0; t < tiles; t++) wl.push_back(make_uint2((unsigned)si, (unsigned)t));
         }
     }
 
@@ -914,6 +1320,15 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
         b->d_work.push_back(d);
         b->phase_blocks.push_back((unsigned)w.size());
     }
+    for (auto &w : work_reg) {
+        uint2 *d = nullptr;
+        rc = upload(&d, w.data(), w.size() * sizeof(uint2));
+        if (rc != QS_OK) return rc;
+        b->d_work_reg.push_back(d);
+        b->phase_blocks_reg.push_back((unsigned)w.size());
+    }
+    up(&b->d_phases, phases);
+    if (rc != QS_OK) return rc;
     if ((rc = upload(&b->d_epart, nullptr, sizeof(double) * 2 * bm_circ.size())) != QS_OK) return rc;
     if ((rc = upload(&b->d_energy, nullptr, sizeof(double) * 2 * b->circs.size())) != QS_OK) return rc;
     if ((rc = upload(&b->d_gpart, nullptr, sizeof(double) * 2 * gfirst.back())) != QS_OK) return rc;
