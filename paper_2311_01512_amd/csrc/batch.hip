@@ -1209,23 +1209,43 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
             d.ph_begin = d.ph_end = (int)phases.size();
             if (d.qn >= kRegMinQubits) {
                 // register phases: at most 3 operator coordinates and
-                // kPhaseRotMax rotations each, operators kept in order
-                int k = d.op_begin;
-                while (k < d.op_end) {
+                // kPhaseRotMax rotations each; a phase takes, in order, every
+                // remaining operator that fits it and shares no qubit with a
+                // remaining operator it jumps over (the step's operators are
+                // regrouped by phase)
+                std::vector<DOp> seg(ops.begin() + d.op_begin, ops.begin() + d.op_end), out;
+                std::vector<char> used(seg.size(), 0);
+                auto support = [](const DOp &x) {
+                    return (1ULL << x.q0) | (x.kind == BOP_CZ ? (1ULL << x.q1) : 0ULL);
+                };
+                while (out.size() < seg.size()) {
                     BPhase ph{};
                     std::vector<int> R;
                     int nrot = 0;
-                    ph.op_begin = k;
-                    for (; k < d.op_end; k++) {
-                        DOp &x = ops[k];
-                        if (x.kind == BOP_CZ) continue;
-                        const bool in = std::find(R.begin(), R.end(), x.pos0) != R.end();
-                        if (!in && R.size() == 3) break;
-                        if (x.kind == BOP_ROT && nrot == kPhaseRotMax) break;
-                        if (!in) R.push_back(x.pos0);
-                        if (x.kind == BOP_ROT) x.slot = nrot++;
+                    uint64_t blocked = 0;
+                    const size_t first = out.size();
+                    for (size_t i = 0; i < seg.size(); i++) {
+                        if (used[i]) continue;
+                        DOp x = seg[i];
+                        const uint64_t sp = support(x);
+                        bool fits = !(sp & blocked);
+                        if (fits && x.kind != BOP_CZ) {
+                            const bool in = std::find(R.begin(), R.end(), x.pos0) != R.end();
+                            if ((!in && R.size() == 3) || (x.kind == BOP_ROT && nrot == kPhaseRotMax)) fits = false;
+                            if (fits) {
+                                if (!in) R.push_back(x.pos0);
+                                if (x.kind == BOP_ROT) x.slot = nrot++;
+                            }
+                        }
+                        if (fits) {
+                            used[i] = 1;
+                            out.push_back(x);
+                        } else {
+                            blocked |= sp;
+                        }
                     }
-                    ph.op_end = k;
+                    ph.op_begin = d.op_begin + (int)first;
+                    ph.op_end = d.op_begin + (int)out.size();
                     for (int cc = d.qn - 1; R.size() < 3; cc--)
                         if (std::find(R.begin(), R.end(), cc) == R.end()) R.push_back(cc);
                     std::vector<int> sorted_r = R;
@@ -1234,11 +1254,12 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
                         ph.rc[j] = R[j];
                         ph.lo[j] = (1u << sorted_r[j]) - 1u;
                     }
-                    for (int kk = ph.op_begin; kk < ph.op_end; kk++)
-                        if (ops[kk].kind != BOP_CZ)
-                            ops[kk].rbit = (int)(std::find(R.begin(), R.end(), ops[kk].pos0) - R.begin());
+                    for (size_t kk = first; kk < out.size(); kk++)
+                        if (out[kk].kind != BOP_CZ)
+                            out[kk].rbit = (int)(std::find(R.begin(), R.end(), out[kk].pos0) - R.begin());
                     phases.push_back(ph);
                 }
+                std::copy(out.begin(), out.end(), ops.begin() + d.op_begin);
                 d.ph_end = (int)phases.size();
             }
             step_index[ci].push_back((int)steps.size());
