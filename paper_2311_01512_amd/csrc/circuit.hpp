@@ -80,6 +80,7 @@ struct ROp {
     uint32_t hsel;                  // matrix-core gate: 2 bits per register, rho[u] at (c4, c5)
     double cs, cre, cim;            // gadget: cos(theta), i sin(theta) i^{#Y}
     double pre, pim;                // (cre, cim) times (-1)^parity(x & yz)
+    float fcs, fcre, fcim, fpre, fpim;   // the same in FP32 for complex64 tiles
 };
 
 struct Pass {

@@ -404,6 +404,11 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
                 ro.cim = c.imag();
                 ro.pre = partner * c.real();
                 ro.pim = partner * c.imag();
+                ro.fcs = (float)ro.cs;
+                ro.fcre = (float)ro.cre;
+                ro.fcim = (float)ro.cim;
+                ro.fpre = (float)ro.pre;
+                ro.fpim = (float)ro.pim;
             } else {
                 ro.nc = (int)op->ctrls.size();
                 for (int q = 0; q < ro.nc; q++) {
@@ -654,31 +659,37 @@ __device__ __forceinline__ void reg_gadget(C2<R> (&x)[kRegs], const ROp &op, uin
 {
     const uint32_t st = (uint32_t)(__popcll(base & op.yz) + __popc(tau & op.yzm)) & 1u;
     const R sg = st ? R(-1) : R(1);
-    const R cs = (R)op.cs;
-    const R kr = sg * (R)op.cre, ki = sg * (R)op.cim;   // this thread's sign times i sin(theta) i^{#Y}
+    // uniform constants (scalar registers), in the kernel's precision
+    R cs, cr, ci, pr, pi;
+    if constexpr (std::is_same<R, float>::value) {
+        cs = op.fcs; cr = op.fcre; ci = op.fcim; pr = op.fpre; pi = op.fpim;
+    } else {
+        cs = op.cs; cr = op.cre; ci = op.cim; pr = op.pre; pi = op.pim;
+    }
     if constexpr (FU == 0) {
-        const R pr = cs + kr, mr = cs - kr, mi = -ki;
+        const R kr = sg * cr, ki = sg * ci;   // this thread's sign times i sin(theta) i^{#Y}
+        const R ar0 = cs + kr, ar1 = cs - kr, ai1 = -ki;
 #pragma unroll
         for (int u = 0; u < kRegs; u++) {
             const bool neg = __popc((uint32_t)u & op.gy) & 1;
-            const R ar = neg ? mr : pr, ai = neg ? mi : ki;
+            const R ar = neg ? ar1 : ar0, ai = neg ? ai1 : ki;
             const C2<R> a = x[u];
             x[u] = mk<R>(ar * a.x - ai * a.y, ar * a.y + ai * a.x);
         }
     } else {
         constexpr int HB = 31 - __builtin_clz((unsigned)FU);
-        const R qr = sg * (R)op.pre, qi = sg * (R)op.pim;   // the same for the partner's sign
 #pragma unroll
         for (int u0 = 0; u0 < kRegs; u0++) {
             if ((u0 >> HB) & 1) continue;
             const int u1 = u0 ^ FU;
-            const R pm = (__popc((uint32_t)u0 & op.gy) & 1) ? R(-1) : R(1);   // uniform
+            // sign of (t, u0): this thread's sign times the register parity
+            const R s = (__popc((uint32_t)u0 & op.gy) & 1) ? -sg : sg;
             const C2<R> x0 = x[u0], x1 = x[u1];
-            // x0' = cs x0 + s(u1) c x1,  x1' = cs x1 + s(u0) c x0
-            const C2<R> t1 = mk<R>(qr * x1.x - qi * x1.y, qr * x1.y + qi * x1.x);
-            const C2<R> t0 = mk<R>(kr * x0.x - ki * x0.y, kr * x0.y + ki * x0.x);
-            x[u0] = mk<R>(fma(pm, t1.x, cs * x0.x), fma(pm, t1.y, cs * x0.y));
-            x[u1] = mk<R>(fma(pm, t0.x, cs * x1.x), fma(pm, t0.y, cs * x1.y));
+            // x0' = cs x0 + s(u1) c x1 = cs x0 + s (c (-1)^par(x & yz)) x1,  x1' = cs x1 + s c x0
+            const C2<R> t1 = mk<R>(pr * x1.x - pi * x1.y, pr * x1.y + pi * x1.x);
+            const C2<R> t0 = mk<R>(cr * x0.x - ci * x0.y, cr * x0.y + ci * x0.x);
+            x[u0] = mk<R>(fma(s, t1.x, cs * x0.x), fma(s, t1.y, cs * x0.y));
+            x[u1] = mk<R>(fma(s, t0.x, cs * x1.x), fma(s, t0.y, cs * x1.y));
         }
     }
 }
@@ -733,41 +744,9 @@ template <typename R>
 __device__ __forceinline__ void apply_reg_op(C2<R> (&x)[kRegs], const ROp &op, uint32_t tau, uint64_t base,
                                              const C2<R> *__restrict__ mats)
 {
-    if constexpr (std::is_same<R, float>::value) {
-        if (op.code >= 32 && op.code < 64) {
-            switch (op.code) {
-            case 32: mfma_dense<0>(x, op, tau, base, mats); break;
-            case 33: mfma_dense<1>(x, op, tau, base, mats); break;
-            case 34: mfma_dense<2>(x, op, tau, base, mats); break;
-            case 35: mfma_dense<3>(x, op, tau, base, mats); break;
-            case 36: mfma_dense<4>(x, op, tau, base, mats); break;
-            case 37: mfma_dense<5>(x, op, tau, base, mats); break;
-            default: mfma_dense<6>(x, op, tau, base, mats); break;
-            }
-            return;
-        }
-    }
+    constexpr bool f32 = std::is_same<R, float>::value;
     const C2<R> *m = mats + op.mat;
-    if (op.code >= 64) {
-        switch (op.code - 64) {
-        case 4 * 1: reg_sparse<R, 1, 0>(x, m); break;
-        case 4 * 2: reg_sparse<R, 2, 0>(x, m); break;
-        case 4 * 4: reg_sparse<R, 4, 0>(x, m); break;
-        case 4 * 3: reg_sparse<R, 3, 0>(x, m); break;
-        case 4 * 3 + 1: reg_sparse<R, 3, 1>(x, m); break;
-        case 4 * 3 + 2: reg_sparse<R, 3, 2>(x, m); break;
-        case 4 * 3 + 3: reg_sparse<R, 3, 3>(x, m); break;
-        case 4 * 5: reg_sparse<R, 5, 0>(x, m); break;
-        case 4 * 5 + 1: reg_sparse<R, 5, 1>(x, m); break;
-        case 4 * 5 + 2: reg_sparse<R, 5, 2>(x, m); break;
-        case 4 * 5 + 3: reg_sparse<R, 5, 3>(x, m); break;
-        case 4 * 6: reg_sparse<R, 6, 0>(x, m); break;
-        case 4 * 6 + 1: reg_sparse<R, 6, 1>(x, m); break;
-        case 4 * 6 + 2: reg_sparse<R, 6, 2>(x, m); break;
-        default: reg_sparse<R, 6, 3>(x, m); break;
-        }
-        return;
-    }
+    // one switch (a jump table) over every operator code
     switch (op.code) {
     case 1: reg_dense<R, 1, false>(x, op, tau, base, m); break;
     case 2: reg_dense<R, 2, false>(x, op, tau, base, m); break;
@@ -790,7 +769,30 @@ __device__ __forceinline__ void apply_reg_op(C2<R> (&x)[kRegs], const ROp &op, u
     case 20: reg_dense<R, 4, true>(x, op, tau, base, m); break;
     case 21: reg_dense<R, 5, true>(x, op, tau, base, m); break;
     case 22: reg_dense<R, 6, true>(x, op, tau, base, m); break;
-    default: reg_dense<R, 7, true>(x, op, tau, base, m); break;
+    case 23: reg_dense<R, 7, true>(x, op, tau, base, m); break;
+    case 32: if constexpr (f32) mfma_dense<0>(x, op, tau, base, mats); break;
+    case 33: if constexpr (f32) mfma_dense<1>(x, op, tau, base, mats); break;
+    case 34: if constexpr (f32) mfma_dense<2>(x, op, tau, base, mats); break;
+    case 35: if constexpr (f32) mfma_dense<3>(x, op, tau, base, mats); break;
+    case 36: if constexpr (f32) mfma_dense<4>(x, op, tau, base, mats); break;
+    case 37: if constexpr (f32) mfma_dense<5>(x, op, tau, base, mats); break;
+    case 38: if constexpr (f32) mfma_dense<6>(x, op, tau, base, mats); break;
+    case 64 + 4 * 1: reg_sparse<R, 1, 0>(x, m); break;
+    case 64 + 4 * 2: reg_sparse<R, 2, 0>(x, m); break;
+    case 64 + 4 * 4: reg_sparse<R, 4, 0>(x, m); break;
+    case 64 + 4 * 3: reg_sparse<R, 3, 0>(x, m); break;
+    case 64 + 4 * 3 + 1: reg_sparse<R, 3, 1>(x, m); break;
+    case 64 + 4 * 3 + 2: reg_sparse<R, 3, 2>(x, m); break;
+    case 64 + 4 * 3 + 3: reg_sparse<R, 3, 3>(x, m); break;
+    case 64 + 4 * 5: reg_sparse<R, 5, 0>(x, m); break;
+    case 64 + 4 * 5 + 1: reg_sparse<R, 5, 1>(x, m); break;
+    case 64 + 4 * 5 + 2: reg_sparse<R, 5, 2>(x, m); break;
+    case 64 + 4 * 5 + 3: reg_sparse<R, 5, 3>(x, m); break;
+    case 64 + 4 * 6: reg_sparse<R, 6, 0>(x, m); break;
+    case 64 + 4 * 6 + 1: reg_sparse<R, 6, 1>(x, m); break;
+    case 64 + 4 * 6 + 2: reg_sparse<R, 6, 2>(x, m); break;
+    case 64 + 4 * 6 + 3: reg_sparse<R, 6, 3>(x, m); break;
+    default: break;
     }
 }
 
