@@ -182,18 +182,39 @@ __global__ __launch_bounds__(256) void k_dense_mfma(float2 *__restrict__ a, uint
     const uint64_t off_out = ((rq & 1) ? tb.b[2] : 0) | ((rq & 2) ? tb.b[3] : 0);
     const uint64_t num_waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
 
-    for (uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave; tile < num_tiles; tile += num_waves) {
+    // input offsets of this lane's D/4 amplitudes within a group
+    uint64_t in_off[D / 4];
+#pragma unroll
+    for (int s = 0; s < D / 4; s++) {
+        uint64_t o = off_in;
+#pragma unroll
+        for (int p = 2; p < K; p++)
+            if ((s >> (p - 2)) & 1) o |= tb.b[p];
+        in_off[s] = o;
+    }
+    uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (tile >= num_tiles) return;
+    // software pipeline: the next tile's amplitudes are loaded while this
+    // tile's MFMAs run (a wave walks tiles tile + k num_waves); the first
+    // tile is waited for before the loop, so the loop never waits on stores
+    float2 x[D / 4];
+    {
+        const uint64_t b0 = insert_zeros(tile * 16 + col, plan) | ctrl_mask;
+#pragma unroll
+        for (int s = 0; s < D / 4; s++) x[s] = a[b0 | in_off[s]];
+#pragma unroll
+        for (int s = 0; s < D / 4; s++) asm volatile("" ::"v"(x[s].x), "v"(x[s].y));
+    }
+    for (; tile < num_tiles; tile += num_waves) {
         // keep the LDS operand reads inside the loop (no hoisting into registers)
         asm volatile("" ::: "memory");
         const uint64_t base = insert_zeros(tile * 16 + col, plan) | ctrl_mask;
-        float2 x[D / 4];
+        const bool more = tile + num_waves < num_tiles;
+        float2 nx[D / 4];
+        if (more) {
+            const uint64_t nb = insert_zeros((tile + num_waves) * 16 + col, plan) | ctrl_mask;
 #pragma unroll
-        for (int s = 0; s < D / 4; s++) {
-            uint64_t o = off_in;
-#pragma unroll
-            for (int p = 2; p < K; p++)
-                if ((s >> (p - 2)) & 1) o |= tb.b[p];
-            x[s] = a[base | o];
+            for (int s = 0; s < D / 4; s++) nx[s] = a[nb | in_off[s]];
         }
         f32x4 acc[MB];
 #pragma unroll
@@ -221,6 +242,10 @@ __global__ __launch_bounds__(256) void k_dense_mfma(float2 *__restrict__ a, uint
                     if ((m >> (p - 4)) & 1) o |= tb.b[p];
                 a[base | o] = make_float2(acc[m][i], acc[m + D / 16][i]);
             }
+        }
+        if (more) {
+#pragma unroll
+            for (int s = 0; s < D / 4; s++) x[s] = nx[s];
         }
     }
 }

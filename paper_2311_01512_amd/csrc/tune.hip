@@ -24,17 +24,23 @@ int mfma_preference()
     return pref;
 }
 
-uint64_t mfma_block_cap(int)
+uint64_t mfma_block_cap(int k)
 {
-    static const uint64_t cap = [] {
+    static const uint64_t forced = [] {
         const char *e = std::getenv("QS_MFMA_BLOCKS");
         if (e) {
             const unsigned long long v = std::strtoull(e, nullptr, 10);
             if (v > 0) return (uint64_t)v;
         }
-        return (uint64_t)1 << 30;
+        return (uint64_t)0;
     }();
-    return cap;
+    if (forced) return forced;
+    // measured on MI355X at 28 qubits: one tile per wave is best for 4
+    // targets; 5 and 6 targets do better with waves that walk several tiles
+    // (the 16-64 KiB A operand is staged into LDS once per block)
+    if (k >= 6) return 2048;
+    if (k == 5) return 8192;
+    return (uint64_t)1 << 30;
 }
 
 int tile_low_qubits(int precision)
