@@ -236,6 +236,79 @@ int oracle_apply_pauli_gadget(cplx *psi, int N, const int *targs,
     return OR_OK;
 }
 
+/*
+ * SWAP gate (Sec. "Swap gate"): an amplitude whose bits t1 and t2 differ
+ * takes the value of the amplitude with both bits flipped; the others keep
+ * theirs.  Each changed pair is visited once, from its member with bit t1
+ * set and bit t2 clear.
+ */
+int oracle_apply_swap(cplx *psi, int N, int t1, int t2)
+{
+    const int t[2] = {t1, t2};
+    if (check_qubits(t, 2, N) != OR_OK)
+        return OR_ERR;
+    const uint64_t both = (1ULL << t1) | (1ULL << t2);
+    const int64_t dim = (int64_t)(1ULL << N);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < dim; i++) {
+        if (get_bit((uint64_t)i, t1) == 1 && get_bit((uint64_t)i, t2) == 0) {
+            const uint64_t j = (uint64_t)i ^ both;
+            const cplx tmp = psi[i];
+            psi[i] = psi[j];
+            psi[j] = tmp;
+        }
+    }
+    return OR_OK;
+}
+
+/*
+ * Pauli tensor (Sec. "Pauli tensor", Eq. "pauli_tensor_amp_update"):
+ * amplitude i becomes beta_{i'} a_{i'}, where i' is i with every X/Y target
+ * bit flipped and beta_x = eta (-1)^{f(x)}, eta = i^{#Y}, f(x) the number of
+ * Y/Z targets whose bit is 1 in x.  Written out of place through a copy so
+ * the update reads only old amplitudes.
+ */
+int oracle_apply_pauli_tensor(cplx *psi, int N, const int *targs, const int *paulis, int n)
+{
+    uint64_t xy, yz;
+    int ny;
+    if (pauli_masks(targs, paulis, n, N, &xy, &yz, &ny) != OR_OK)
+        return OR_ERR;
+    const cplx eta = i_pow(ny);
+    const int64_t dim = (int64_t)(1ULL << N);
+    cplx *old = (cplx *)malloc(sizeof(cplx) * (size_t)dim);
+    if (!old)
+        return OR_ERR;
+    memcpy(old, psi, sizeof(cplx) * (size_t)dim);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < dim; i++) {
+        const uint64_t src = (uint64_t)i ^ xy;
+        psi[i] = pauli_beta(src, yz, eta) * old[src];
+    }
+    free(old);
+    return OR_OK;
+}
+
+/*
+ * Phase gadget exp(i theta Z..Z) (Sec. "Phase gadget",
+ * Eq. "phase_gadget_amp_change"): amplitude i is multiplied by
+ * exp(i theta s_i), s_i = +1 when an even number of the targets are 1 in i,
+ * else -1.
+ */
+int oracle_apply_phase_gadget(cplx *psi, int N, const int *targs, int n, double theta)
+{
+    if (n < 1 || check_qubits(targs, n, N) != OR_OK)
+        return OR_ERR;
+    const uint64_t mask = bit_mask(targs, n);
+    const int64_t dim = (int64_t)(1ULL << N);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < dim; i++) {
+        const double s = parity((uint64_t)i & mask) ? -1.0 : 1.0;
+        psi[i] *= cexp(I * theta * s);
+    }
+    return OR_OK;
+}
+
 /* ---- density matrices (Choi vectors) ---------------------------------- */
 
 /*
@@ -287,6 +360,58 @@ int oracle_dm_apply_pauli_gadget(cplx *rho, int N, const int *targs,
             th = -th;
     }
     return oracle_apply_pauli_gadget(rho, 2 * N, t2, paulis, n, th);
+}
+
+/*
+ * SWAP, Pauli tensor and phase gadget on a density matrix
+ * (Alg. "distrib_dens_matr_specific_unitaries"), each the statevector
+ * routine on the Choi vector twice, using conj(SWAP) = SWAP,
+ * conj(P) = (-1)^m P for m Y operators, and
+ * conj(exp(i theta Z..Z)) = exp(-i theta Z..Z).
+ */
+int oracle_dm_apply_swap(cplx *rho, int N, int t1, int t2)
+{
+    const int t[2] = {t1, t2};
+    if (check_qubits(t, 2, N) != OR_OK)
+        return OR_ERR;
+    if (oracle_apply_swap(rho, 2 * N, t1, t2) != OR_OK)
+        return OR_ERR;
+    return oracle_apply_swap(rho, 2 * N, t1 + N, t2 + N);
+}
+
+int oracle_dm_apply_pauli_tensor(cplx *rho, int N, const int *targs, const int *paulis, int n)
+{
+    if (n > 32 || check_qubits(targs, n, N) != OR_OK)
+        return OR_ERR;
+    if (oracle_apply_pauli_tensor(rho, 2 * N, targs, paulis, n) != OR_OK)
+        return OR_ERR;
+    int t2[64];
+    int m = 0;
+    for (int q = 0; q < n; q++) {
+        t2[q] = targs[q] + N;
+        if (paulis[q] == 2)
+            m = !m;
+    }
+    if (oracle_apply_pauli_tensor(rho, 2 * N, t2, paulis, n) != OR_OK)
+        return OR_ERR;
+    if (m) {
+        const int64_t dim = (int64_t)(1ULL << (2 * N));
+        for (int64_t j = 0; j < dim; j++)
+            rho[j] *= -1.0;
+    }
+    return OR_OK;
+}
+
+int oracle_dm_apply_phase_gadget(cplx *rho, int N, const int *targs, int n, double theta)
+{
+    if (n < 1 || n > 32 || check_qubits(targs, n, N) != OR_OK)
+        return OR_ERR;
+    if (oracle_apply_phase_gadget(rho, 2 * N, targs, n, theta) != OR_OK)
+        return OR_ERR;
+    int t2[64];
+    for (int q = 0; q < n; q++)
+        t2[q] = targs[q] + N;
+    return oracle_apply_phase_gadget(rho, 2 * N, t2, n, -theta);
 }
 
 /*

@@ -30,6 +30,12 @@ def lib():
             "oracle_apply_pauli_gadget": [P, i, P, P, i, d],
             "oracle_dm_apply_gate": [P, i, P, i, P, i, P],
             "oracle_dm_apply_pauli_gadget": [P, i, P, P, i, d],
+            "oracle_apply_swap": [P, i, i, i],
+            "oracle_dm_apply_swap": [P, i, i, i],
+            "oracle_apply_pauli_tensor": [P, i, P, P, i],
+            "oracle_dm_apply_pauli_tensor": [P, i, P, P, i],
+            "oracle_apply_phase_gadget": [P, i, P, i, d],
+            "oracle_dm_apply_phase_gadget": [P, i, P, i, d],
             "oracle_build_superop": [P, i, i, P],
             "oracle_dm_apply_superop": [P, i, P, i, P],
             "oracle_dm_apply_kraus": [P, i, P, i, P, i],
@@ -111,6 +117,31 @@ def apply_pauli_gadget(psi, targs, paulis, theta):
     return psi
 
 
+def apply_swap(psi, t1, t2):
+    psi = _cplx(psi)
+    N = _num_qubits(psi, False)
+    _check(lib().oracle_apply_swap(_ptr(psi), N, int(t1), int(t2)), "apply_swap")
+    return psi
+
+
+def apply_pauli_tensor(psi, targs, paulis):
+    psi = _cplx(psi)
+    N = _num_qubits(psi, False)
+    t, p = _ints(targs), _ints(paulis)
+    if len(t) != len(p):
+        raise ValueError("one Pauli code per target")
+    _check(lib().oracle_apply_pauli_tensor(_ptr(psi), N, _ptr(t), _ptr(p), len(t)), "apply_pauli_tensor")
+    return psi
+
+
+def apply_phase_gadget(psi, targs, theta):
+    psi = _cplx(psi)
+    N = _num_qubits(psi, False)
+    t = _ints(targs)
+    _check(lib().oracle_apply_phase_gadget(_ptr(psi), N, _ptr(t), len(t), float(theta)), "apply_phase_gadget")
+    return psi
+
+
 def sv_expec_pauli_sum(psi, codes, coeffs):
     psi = _cplx(psi)
     N = _num_qubits(psi, False)
@@ -155,6 +186,32 @@ def dm_apply_pauli_gadget(rho, targs, paulis, theta):
     t, p = _ints(targs), _ints(paulis)
     _check(lib().oracle_dm_apply_pauli_gadget(_ptr(rho), N, _ptr(t), _ptr(p), len(t), float(theta)),
            "dm_apply_pauli_gadget")
+    return rho
+
+
+def dm_apply_swap(rho, t1, t2):
+    rho = _cplx(rho)
+    N = _num_qubits(rho, True)
+    _check(lib().oracle_dm_apply_swap(_ptr(rho), N, int(t1), int(t2)), "dm_apply_swap")
+    return rho
+
+
+def dm_apply_pauli_tensor(rho, targs, paulis):
+    rho = _cplx(rho)
+    N = _num_qubits(rho, True)
+    t, p = _ints(targs), _ints(paulis)
+    if len(t) != len(p):
+        raise ValueError("one Pauli code per target")
+    _check(lib().oracle_dm_apply_pauli_tensor(_ptr(rho), N, _ptr(t), _ptr(p), len(t)), "dm_apply_pauli_tensor")
+    return rho
+
+
+def dm_apply_phase_gadget(rho, targs, theta):
+    rho = _cplx(rho)
+    N = _num_qubits(rho, True)
+    t = _ints(targs)
+    _check(lib().oracle_dm_apply_phase_gadget(_ptr(rho), N, _ptr(t), len(t), float(theta)),
+           "dm_apply_phase_gadget")
     return rho
 
 
@@ -293,6 +350,12 @@ def run_ops(state, ops, density=False):
         elif kind == "gadget":
             (dm_apply_pauli_gadget if density else apply_pauli_gadget)(state, op["targs"], op["paulis"],
                                                                        op["theta"])
+        elif kind == "swap":
+            (dm_apply_swap if density else apply_swap)(state, op["targs"][0], op["targs"][1])
+        elif kind == "pauli_tensor":
+            (dm_apply_pauli_tensor if density else apply_pauli_tensor)(state, op["targs"], op["paulis"])
+        elif kind == "phase_gadget":
+            (dm_apply_phase_gadget if density else apply_phase_gadget)(state, op["targs"], op["theta"])
         elif kind == "kraus":
             if not density:
                 raise ValueError("Kraus map needs a density matrix")

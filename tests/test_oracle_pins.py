@@ -490,6 +490,82 @@ def test_param_shift_gradient_closed_form_and_fd():
     assert np.abs(g - fd).max() < 1e-8
 
 
+# ---- SWAP, Pauli tensor, phase gadget (statevector and density matrix) ------------
+
+SWAP4 = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], dtype=complex)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_swap_matches_dense_and_cnot_decomposition(seed):
+    rng = rng_for(700 + seed)
+    N = int(rng.integers(2, 8))
+    t1, t2 = (int(x) for x in rng.permutation(N)[:2])
+    psi = rand_state(rng, N)
+    want = D.embed(N, [t1, t2], SWAP4) @ psi
+    X = D.PAULIS[1]
+    cnots = D.gate_operator(N, [t1], [t2], X) @ D.gate_operator(N, [t2], [t1], X) @ D.gate_operator(N, [t1], [t2], X)
+    assert np.abs(cnots @ psi - want).max() < TOL
+    got = oracle.apply_swap(psi.copy(), t1, t2)
+    assert np.abs(got - want).max() < TOL
+    # a basis state moves to the index with bits t1 and t2 exchanged
+    i = int(rng.integers(0, 1 << N))
+    j = i & ~((1 << t1) | (1 << t2))
+    j |= ((i >> t1) & 1) << t2 | ((i >> t2) & 1) << t1
+    e = np.zeros(1 << N, dtype=complex)
+    e[i] = 1
+    moved = oracle.apply_swap(e, t1, t2)
+    assert moved[j] == 1 and np.count_nonzero(moved) == 1
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_pauli_tensor_matches_dense(seed):
+    rng = rng_for(720 + seed)
+    N = int(rng.integers(1, 8))
+    w = int(rng.integers(1, N + 1))
+    t = [int(x) for x in rng.permutation(N)[:w]]
+    p = [int(x) for x in rng.integers(0, 4, size=w)]
+    psi = rand_state(rng, N)
+    want = D.pauli_operator(N, t, p) @ psi
+    got = oracle.apply_pauli_tensor(psi.copy(), t, p)
+    assert np.abs(got - want).max() < TOL
+    # a Pauli string squares to the identity
+    assert np.abs(oracle.apply_pauli_tensor(got, t, p) - psi).max() < TOL
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_phase_gadget_matches_expm(seed):
+    rng = rng_for(740 + seed)
+    N = int(rng.integers(1, 8))
+    w = int(rng.integers(1, N + 1))
+    t = [int(x) for x in rng.permutation(N)[:w]]
+    theta = rng.uniform(-7, 7)
+    psi = rand_state(rng, N)
+    want = D.gadget_operator(N, t, [3] * w, theta) @ psi
+    got = oracle.apply_phase_gadget(psi.copy(), t, theta)
+    assert np.abs(got - want).max() < TOL
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dm_special_unitaries_match_dense(seed):
+    """Pins conj(SWAP) = SWAP, conj(P) = (-1)^m P and
+    conj(exp(i theta Z..Z)) = exp(-i theta Z..Z) on the Choi vector."""
+    rng = rng_for(760 + seed)
+    N = int(rng.integers(2, 6))
+    rho = rand_dm(rng, N)
+    t1, t2 = (int(x) for x in rng.permutation(N)[:2])
+    S = D.embed(N, [t1, t2], SWAP4)
+    assert np.abs(oracle.dm_apply_swap(D.choi(rho), t1, t2) - D.choi(S @ rho @ S.conj().T)).max() < TOL
+    w = int(rng.integers(1, N + 1))
+    t = [int(x) for x in rng.permutation(N)[:w]]
+    p = [int(x) for x in rng.integers(1, 4, size=w)]
+    p[0] = 2                                         # at least one Y: the sign matters
+    P = D.pauli_operator(N, t, p)
+    assert np.abs(oracle.dm_apply_pauli_tensor(D.choi(rho), t, p) - D.choi(P @ rho @ P.conj().T)).max() < TOL
+    theta = rng.uniform(-4, 4)
+    G = D.gadget_operator(N, t, [3] * w, theta)
+    assert np.abs(oracle.dm_apply_phase_gadget(D.choi(rho), t, theta) - D.choi(G @ rho @ G.conj().T)).max() < TOL
+
+
 # ---- argument checks --------------------------------------------------------------------
 
 def test_oracle_rejects_bad_arguments():
@@ -505,3 +581,9 @@ def test_oracle_rejects_bad_arguments():
         oracle.apply_pauli_gadget(psi, [0], [4], 0.1)        # bad Pauli code
     with pytest.raises(ValueError):
         oracle.partial_trace(oracle.zero_state(2, density=True), [0, 1])   # nothing left
+    with pytest.raises(ValueError):
+        oracle.apply_swap(psi, 1, 1)                         # same qubit twice
+    with pytest.raises(ValueError):
+        oracle.apply_pauli_tensor(psi, [0, 1], [1, 5])       # bad Pauli code
+    with pytest.raises(ValueError):
+        oracle.dm_apply_phase_gadget(oracle.zero_state(2, density=True), [2], 0.1)   # qubit 2 of 2
