@@ -132,12 +132,56 @@ int qs_apply_multi_ctrl_multi_targ_unitary(qs_qureg *q, const int *ctrls, int nu
 /*
  * Pauli gadget exp(i theta P), P = tensor of paulis[q] on targs[q]
  * (Sec. "Pauli gadget"; Sec. "Phase gadget" when P has no X or Y).  Codes
- * 0..3; identity entries are ignored.  On a density matrix the gadget is
- * applied to the targets, then to the targets shifted by N with angle
- * (-1)^(m+1) theta, m = number of Y (Alg. "distrib_dens_matr_specific_unitaries").
+ * 0..3; identity entries are ignored.  On a density matrix it applies
+ * rho -> G rho G^dagger: the gadget on the targets and, with angle
+ * (-1)^(m+1) theta (m = number of Y), on the targets shifted by N
+ * (Alg. "distrib_dens_matr_specific_unitaries"), fused into one pass over
+ * the Choi vector.  Targets distinct and < N (QS_E_ARG).
  */
 int qs_apply_pauli_gadget(qs_qureg *q, const int *targs, const int *paulis,
                           int num_targs, double theta);
+
+/*
+ * SWAP gate on qubits qubit1 != qubit2 (Sec. "Swap gate"): amplitudes whose
+ * two bits differ trade places with the amplitude that has both bits
+ * flipped; no floating-point work, and only the moved half of the state is
+ * written.  On a density matrix, rho -> SWAP rho SWAP: the same swap on the
+ * column bits t + N, since conj(SWAP) = SWAP (Alg.
+ * "distrib_dens_matr_specific_unitaries"), in the same pass.
+ * Qubits distinct and < N (QS_E_ARG).  Asynchronous on the qureg's stream.
+ */
+int qs_apply_swap(qs_qureg *q, int qubit1, int qubit2);
+
+/*
+ * num_pairs disjoint SWAPs (qubits1[k], qubits2[k]) at once: the qubit
+ * remapping that moves a many-target gate's high targets onto low qubits
+ * (Sec. "Many-target gate", the SWAP conjugation of an upper-targeting
+ * gate).  Up to 3 index-bit pairs share a pass (a density matrix counts
+ * each pair twice).  All 2 num_pairs qubits distinct and < N (QS_E_ARG).
+ */
+int qs_apply_multi_swap(qs_qureg *q, const int *qubits1, const int *qubits2, int num_pairs);
+
+/*
+ * Pauli tensor P = tensor of paulis[q] (codes 0..3) on targs[q]
+ * (Sec. "Pauli tensor", Eq. "pauli_tensor_amp_update"): amplitude i becomes
+ * beta a_{i'}, i' = i with the X/Y target bits flipped, beta a unit
+ * (+-1, +-i) fixed by i' and the Y/Z targets; one pass, no products.  On a
+ * density matrix, rho -> P rho P^dagger: P on the targets and
+ * conj(P) = (-1)^m P on the targets shifted by N (Eq.
+ * "distrib_pauli_tensor_conj"), one pass.  Targets distinct and < N,
+ * codes in 0..3 (QS_E_ARG).
+ */
+int qs_apply_pauli_tensor(qs_qureg *q, const int *targs, const int *paulis, int num_targs);
+
+/*
+ * Phase gadget exp(i theta Z (x) ... (x) Z) on targs (Sec. "Phase gadget",
+ * Eq. "phase_gadget_amp_change"): amplitude i is multiplied by
+ * exp(i theta s_i), s_i = -1 when an odd number of the targets are 1 in i,
+ * else +1.  On a density matrix, exp(i theta Z..Z) on the targets and
+ * exp(-i theta Z..Z) on the targets shifted by N, one diagonal pass.
+ * Targets distinct and < N (QS_E_ARG).
+ */
+int qs_apply_phase_gadget(qs_qureg *q, const int *targs, int num_targs, double theta);
 
 /*
  * Superoperator S (4^n x 4^n, row-major (re, im) doubles) on targets t of a

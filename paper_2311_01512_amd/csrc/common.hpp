@@ -168,6 +168,9 @@ int launch_dense(qs_qureg *q, const std::vector<int> &ctrls, const std::vector<i
 int apply_raw_gate(qs_qureg *q, const std::vector<int> &ctrls, const std::vector<int> &targs,
                    const std::vector<cd> &M);
 int apply_raw_gadget(qs_qureg *q, const std::vector<int> &targs, const std::vector<int> &paulis, double theta);
+// rho -> G rho G^dagger for the Pauli gadget G on a density matrix, one pass
+// (special.hip).
+int apply_density_gadget(qs_qureg *q, const int *targs, const int *paulis, int num_targs, double theta);
 std::vector<cd> superop_of_kraus(const std::vector<std::vector<cd>> &ks, int n);
 
 // ---- tuning knobs (tune.hip) ---------------------------------------------------

@@ -533,14 +533,8 @@ int qs_apply_pauli_gadget(qs_qureg *q, const int *targs, const int *paulis, int 
     std::vector<int> t(targs, targs + num_targs), p(paulis, paulis + num_targs);
     for (int x : p)
         if (x < 0 || x > 3) return fail(QS_E_ARG, "Pauli codes are 0..3");
-    int rc = apply_raw_gadget(q, t, p, theta);
-    if (rc != QS_OK || !q->is_density) return rc;
-    // conj(exp(i theta P)) = exp(i (-1)^{m+1} theta P), m = #Y, on t + N
-    double th = -theta;
-    for (int x : p)
-        if (x == 2) th = -th;
-    for (int &x : t) x += q->num_qubits;
-    return apply_raw_gadget(q, t, p, th);
+    if (q->is_density) return apply_density_gadget(q, targs, paulis, num_targs, theta);
+    return apply_raw_gadget(q, t, p, theta);
 }
 
 int qs_apply_superop(qs_qureg *q, const int *targs, int num_targs, const double *superop)

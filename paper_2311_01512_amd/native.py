@@ -54,6 +54,10 @@ _SIGS = {
     "qs_get_amps": [_P, _U64, _P, _U64],
     "qs_apply_multi_ctrl_multi_targ_unitary": [_P, _P, _I, _P, _I, _P],
     "qs_apply_pauli_gadget": [_P, _P, _P, _I, _D],
+    "qs_apply_swap": [_P, _I, _I],
+    "qs_apply_multi_swap": [_P, _P, _P, _I],
+    "qs_apply_pauli_tensor": [_P, _P, _P, _I],
+    "qs_apply_phase_gadget": [_P, _P, _I, _D],
     "qs_apply_superop": [_P, _P, _I, _P],
     "qs_apply_kraus_map": [_P, _P, _I, _P, _I],
     "qs_calc_partial_trace": [_P, _P, _I, _P],
@@ -194,6 +198,29 @@ def qs_apply_pauli_gadget(q, targs, paulis, theta):
     if t.size != p.size:
         raise ValueError("targs and paulis differ in length")
     check(lib.qs_apply_pauli_gadget(q, ptr(t), ptr(p), t.size, float(theta)), "qs_apply_pauli_gadget")
+
+
+def qs_apply_swap(q, qubit1, qubit2):
+    check(lib.qs_apply_swap(q, int(qubit1), int(qubit2)), "qs_apply_swap")
+
+
+def qs_apply_multi_swap(q, qubits1, qubits2):
+    a, b = ints(qubits1), ints(qubits2)
+    if a.size != b.size:
+        raise ValueError("qubits1 and qubits2 differ in length")
+    check(lib.qs_apply_multi_swap(q, ptr(a), ptr(b), a.size), "qs_apply_multi_swap")
+
+
+def qs_apply_pauli_tensor(q, targs, paulis):
+    t, p = ints(targs), ints(paulis)
+    if t.size != p.size:
+        raise ValueError("targs and paulis differ in length")
+    check(lib.qs_apply_pauli_tensor(q, ptr(t), ptr(p), t.size), "qs_apply_pauli_tensor")
+
+
+def qs_apply_phase_gadget(q, targs, theta):
+    t = ints(targs)
+    check(lib.qs_apply_phase_gadget(q, ptr(t), t.size, float(theta)), "qs_apply_phase_gadget")
 
 
 def qs_apply_superop(q, targs, superop):

@@ -85,6 +85,22 @@ class Qureg:
         N.qs_apply_pauli_gadget(self._q, targs, paulis, theta)
         return self
 
+    def apply_swap(self, qubit1, qubit2):
+        N.qs_apply_swap(self._q, qubit1, qubit2)
+        return self
+
+    def apply_multi_swap(self, qubits1, qubits2):
+        N.qs_apply_multi_swap(self._q, qubits1, qubits2)
+        return self
+
+    def apply_pauli_tensor(self, targs, paulis):
+        N.qs_apply_pauli_tensor(self._q, targs, paulis)
+        return self
+
+    def apply_phase_gadget(self, targs, theta):
+        N.qs_apply_phase_gadget(self._q, targs, theta)
+        return self
+
     def apply_superop(self, targs, superop):
         N.qs_apply_superop(self._q, targs, superop)
         return self
@@ -94,7 +110,8 @@ class Qureg:
         return self
 
     def run_ops(self, ops):
-        """Apply op dicts ({"op": "unitary"|"gadget"|"kraus", ...}) in order."""
+        """Apply op dicts ({"op": "unitary"|"gadget"|"kraus"|"swap"|"pauli_tensor"|
+        "phase_gadget", ...}) in order."""
         for op in ops:
             kind = op["op"]
             if kind == "unitary":
@@ -103,6 +120,12 @@ class Qureg:
                 N.qs_apply_pauli_gadget(self._q, op["targs"], op["paulis"], op["theta"])
             elif kind == "kraus":
                 N.qs_apply_kraus_map(self._q, op["targs"], op["kraus"])
+            elif kind == "swap":
+                N.qs_apply_swap(self._q, op["targs"][0], op["targs"][1])
+            elif kind == "pauli_tensor":
+                N.qs_apply_pauli_tensor(self._q, op["targs"], op["paulis"])
+            elif kind == "phase_gadget":
+                N.qs_apply_phase_gadget(self._q, op["targs"], op["theta"])
             else:
                 raise ValueError(f"unknown op {kind}")
         return self

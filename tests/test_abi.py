@@ -50,6 +50,12 @@ def test_host_side_argument_checks(lib):
     assert lib.qs_create_qureg(21, 1, 1, None, None, C.byref(out)) == -3       # 2^42 amplitudes
     lib.qs_apply_pauli_gadget.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double]
     assert lib.qs_apply_pauli_gadget(None, None, None, 1, 0.1) == -1           # null qureg
+    lib.qs_apply_swap.argtypes = [C.c_void_p, C.c_int, C.c_int]
+    assert lib.qs_apply_swap(None, 0, 1) == -1                                 # null qureg
+    lib.qs_apply_pauli_tensor.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+    assert lib.qs_apply_pauli_tensor(None, None, None, 1) == -1
+    lib.qs_apply_phase_gadget.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_double]
+    assert lib.qs_apply_phase_gadget(None, None, 1, 0.1) == -1
     assert lib.qs_destroy_qureg(None) == 0
 
 
@@ -64,6 +70,10 @@ def test_binding_rejects_bad_shapes():
         N.qs_apply_superop(None, [0], np.eye(2))
     with pytest.raises(ValueError):
         N.qs_apply_pauli_gadget(None, [0, 1], [1], 0.2)
+    with pytest.raises(ValueError):
+        N.qs_apply_pauli_tensor(None, [0, 1], [1])
+    with pytest.raises(ValueError):
+        N.qs_apply_multi_swap(None, [0, 1], [2])
 
 
 def test_circuit_recording_checks(lib):

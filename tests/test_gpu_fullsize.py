@@ -118,6 +118,10 @@ def test_28_qubits_single_ops_every_kernel(qs):
         [{"op": "unitary", "ctrls": (5,), "targs": (27, 2, 9, 14, 1, 22), "matrix": synth.haar_unitary(rng, 64)}],
         [{"op": "gadget", "targs": (0, 5, 27, 13), "paulis": (1, 2, 3, 2), "theta": 0.7}],
         [{"op": "gadget", "targs": (4, 19), "paulis": (3, 3), "theta": -1.3}],
+        [{"op": "swap", "targs": (27, 0)}],
+        [{"op": "swap", "targs": (9, 21)}],
+        [{"op": "pauli_tensor", "targs": (0, 26, 11, 3), "paulis": (2, 1, 3, 2)}],
+        [{"op": "phase_gadget", "targs": (27, 2, 15), "theta": 0.9}],
     ]
     for ops in cases:
         banner(f"28q single op {ops[0]['op']} targs={ops[0]['targs']}")
@@ -142,7 +146,11 @@ def test_14_qubit_density_matrix_sampled(qs):
            {"op": "kraus", "targs": (6,), "kraus": synth.kraus_depolarising_1q(0.04)},
            {"op": "unitary", "ctrls": (13,), "targs": (6,), "matrix": synth.haar_unitary(rng, 2)},
            {"op": "kraus", "targs": (13,), "kraus": synth.kraus_damping_1q(0.08)},
-           {"op": "gadget", "targs": (0, 6, 13), "paulis": (2, 1, 3), "theta": 0.4}]
+           {"op": "gadget", "targs": (0, 6, 13), "paulis": (2, 1, 3), "theta": 0.4},
+           {"op": "swap", "targs": (13, 0)},
+           {"op": "pauli_tensor", "targs": (6, 13), "paulis": (2, 1)},
+           {"op": "phase_gadget", "targs": (0, 13), "theta": -0.8},
+           {"op": "gadget", "targs": (6,), "paulis": (2,), "theta": 1.2}]
     q = qs.Qureg(N, density=True, precision="c128").init_hashed(seed)
     q.run_ops(ops)
     # Choi index bits: Qd on the row half, Qd + N on the column half
