@@ -228,6 +228,41 @@ def bench_channels(q, torch, amp_bytes):
     return res
 
 
+def bench_special(q, torch, amp_bytes, reps=3):
+    """The matrix-free special unitaries on a statevector or density qureg:
+    average ms of `reps` applications and GB/s of the 128-byte lines each
+    must read and write: a SWAP of two high qubits moves half of a
+    statevector in whole lines; a SWAP or multi-SWAP with a qubit inside a
+    line (qubit 0 here) moves part of every line, so every line is read and
+    written; Pauli tensors, phase gadgets and gadgets read and write every
+    amplitude."""
+    n = q.num_qubits
+    if q.density:
+        calls = [("swap_low_high", lambda: q.apply_swap(0, n - 1), 1.0),
+                 ("pauli_tensor_xyz", lambda: q.apply_pauli_tensor([0, 5, n - 1], [1, 2, 3]), 1.0),
+                 ("phase_gadget_3", lambda: q.apply_phase_gadget([1, 6, n - 2], 0.3), 1.0),
+                 ("pauli_gadget_xyz", lambda: q.apply_pauli_gadget([0, 5, n - 1], [1, 2, 3], 0.3), 1.0)]
+    else:
+        calls = [("swap_low_high", lambda: q.apply_swap(0, n - 1), 1.0),
+                 ("swap_high_high", lambda: q.apply_swap(n - 2, n - 1), 0.5),
+                 ("multi_swap_3", lambda: q.apply_multi_swap([0, 1, 2], [n - 1, n - 2, n - 3]), 1.0),
+                 ("pauli_tensor_xyz", lambda: q.apply_pauli_tensor([0, 11, n - 1], [1, 2, 3]), 1.0),
+                 ("phase_gadget_3", lambda: q.apply_phase_gadget([1, 12, n - 2], 0.3), 1.0)]
+    res = {}
+    for name, fn, frac in calls:
+        fn()                                   # untimed first call
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(q.stream)
+        for _ in range(reps):
+            fn()
+        b.record(q.stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / reps
+        byts = 2 * amp_bytes * frac * q.num_amps
+        res[name] = {"ms": ms, "GBps": byts / (ms * 1e-3) / 1e9, "hbm_frac": byts / (ms * 1e-3) / 8e12}
+    return res
+
+
 def bench_density(args, torch, qs, synth):
     """14-qubit density matrix (Choi vector of 2^28 amplitudes): 300 ops of
     Haar unitaries, depolarising, damping and random Kraus maps applied as
@@ -269,7 +304,8 @@ def bench_density(args, torch, qs, synth):
         out[prec] = {"value": logical / step_s, "ms_per_step": step_s * 1e3,
                      "roofline": roofline(kinds, ab, 2 * n),
                      "per_kind": per_kernel_table(kinds, ab),
-                     "channels": bench_channels(q, torch, ab)}
+                     "channels": bench_channels(q, torch, ab),
+                     "special_ops": bench_special(q, torch, ab)}
         if prec == "c128":
             # reference result of the plain FP64 path, from |0><0|, one application
             q.init_zero().run_ops(ops)
@@ -455,6 +491,8 @@ def main():
         "plain_c128": {"value": logical / t128, "ms_per_step": t128 * 1e3, "passes": len(ops),
                        "roofline": roofline(kinds128, 16, n), "per_kernel": per_kernel_table(kinds128, 16)},
         "speedup_fused_c64_vs_plain_c128": t128 / t64,
+        "special_ops_c128": bench_special(q128, torch, 16),
+        "special_ops_c64": bench_special(q64, torch, 8),
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_seconds)

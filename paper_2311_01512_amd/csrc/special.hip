@@ -65,6 +65,104 @@ __global__ __launch_bounds__(256) void k_swap(C2<R> *__restrict__ a, uint64_t nu
     }
 }
 
+// Swaps that involve one of the lowest index bits move amplitudes inside
+// every 128-byte line, so each line is read and written whole whatever the
+// kernel does.  Then a block stages one tile through LDS: the 2^T amplitudes
+// that share every bit outside the tile bits (the pair bits and the lowest
+// other bits), read in runs of consecutive amplitudes (16 bytes per lane),
+// stored in LDS at their permuted local index, and written back in the same
+// runs.
+constexpr int kTileThreads = 256;
+
+struct SwapTilePlan {
+    InsertPlan outer;        // splices the T tile bits into the tile number
+    uint64_t hi_bit[8];      // global mask of each tile-local bit above the lane bits
+    int pairs;               // swapped local-bit pairs
+    int ja[kSwapPairs], jb[kSwapPairs];
+};
+
+// Vectors of V = 16 bytes / amplitude size consecutive amplitudes; local bits
+// 0..L-1 (L = log2(256 V)) are index bits 0..L-1 (lane and vector element),
+// local bits L..T-1 are hi_bit[0..T-L-1].
+template <typename R, int T>
+__global__ __launch_bounds__(kTileThreads) void k_swap_tile(C2<R> *__restrict__ a, SwapTilePlan sp)
+{
+    constexpr int V = 16 / sizeof(C2<R>);
+    constexpr int L = V == 2 ? 9 : 8;
+    constexpr int E = (1 << T) / (kTileThreads * V);   // vectors per thread
+    struct alignas(16) Vec {
+        C2<R> v[V];
+    };
+    __shared__ Vec lds[(1 << T) / V];
+    C2<R> *ldsa = &lds[0].v[0];
+    const uint64_t base = insert_zeros(blockIdx.x, sp.outer) | ((uint64_t)threadIdx.x * V);
+    Vec x[E];
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        uint64_t off = 0;
+#pragma unroll
+        for (int b = 0; b < T - L; b++)
+            if ((k >> b) & 1) off |= sp.hi_bit[b];
+        x[k] = *(const Vec *)&a[base | off];
+    }
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+#pragma unroll
+        for (int e = 0; e < V; e++) {
+            uint32_t m = (threadIdx.x * V + e) + (kTileThreads * V) * k;
+            for (int p = 0; p < sp.pairs; p++) {
+                const uint32_t d = ((m >> sp.ja[p]) ^ (m >> sp.jb[p])) & 1u;
+                m ^= d * ((1u << sp.ja[p]) | (1u << sp.jb[p]));
+            }
+            ldsa[m] = x[k].v[e];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        uint64_t off = 0;
+#pragma unroll
+        for (int b = 0; b < T - L; b++)
+            if ((k >> b) & 1) off |= sp.hi_bit[b];
+        *(Vec *)&a[base | off] = lds[threadIdx.x + kTileThreads * k];
+    }
+}
+
+// Tile bits of a staged swap: the pair bits and the lowest other bits, T in
+// all, with the lane bits among them; false if the register is too small or
+// the pairs leave too few low bits.
+template <typename R, int T>
+static bool launch_swap_tile(qs_qureg *q, const std::vector<int> &b1, const std::vector<int> &b2)
+{
+    constexpr int L = sizeof(C2<R>) == 8 ? 9 : 8;
+    const int n = q->index_bits;
+    if (n < T) return false;
+    std::vector<char> in(n, 0);
+    for (size_t k = 0; k < b1.size(); k++) in[b1[k]] = in[b2[k]] = 1;
+    int need = T - 2 * (int)b1.size();
+    for (int b = 0; b < n && need > 0; b++)
+        if (!in[b]) {
+            in[b] = 1;
+            need--;
+        }
+    std::vector<int> tb;
+    for (int b = 0; b < n; b++)
+        if (in[b]) tb.push_back(b);
+    if ((int)tb.size() != T || tb[L - 1] != L - 1) return false;
+    SwapTilePlan sp{};
+    sp.outer = make_insert_plan(tb);
+    for (int k = 0; k < T - L; k++) sp.hi_bit[k] = 1ULL << tb[L + k];
+    sp.pairs = (int)b1.size();
+    for (int p = 0; p < sp.pairs; p++) {
+        sp.ja[p] = (int)(std::find(tb.begin(), tb.end(), b1[p]) - tb.begin());
+        sp.jb[p] = (int)(std::find(tb.begin(), tb.end(), b2[p]) - tb.begin());
+    }
+    const uint64_t tiles = q->num_amps >> T;
+    hipLaunchKernelGGL((k_swap_tile<R, T>), dim3((unsigned)tiles), dim3(kTileThreads), 0, q->stream,
+                       (C2<R> *)q->amps, sp);
+    return true;
+}
+
 // Applies the disjoint index-bit swaps (lo[k], hi[k]) in launches of at most
 // kSwapPairs pairs.
 static int launch_swaps(qs_qureg *q, const std::vector<int> &b1, const std::vector<int> &b2)
@@ -94,6 +192,18 @@ static int launch_swaps(qs_qureg *q, const std::vector<int> &b1, const std::vect
                 tab.from[tab.num_moves] = off;
                 tab.to[tab.num_moves] = img;
                 tab.num_moves++;
+            }
+        }
+        // a pair bit inside a 128-byte line (16 complex64 or 8 complex128
+        // amplitudes): staged through LDS
+        const int line_bits = q->precision == QS_C64 ? 4 : 3;
+        if (*std::min_element(bits.begin(), bits.end()) < line_bits) {
+            const std::vector<int> c1(b1.begin() + p0, b1.begin() + p0 + P), c2(b2.begin() + p0, b2.begin() + p0 + P);
+            const bool staged = q->precision == QS_C64 ? launch_swap_tile<float, 12>(q, c1, c2)
+                                                       : launch_swap_tile<double, 11>(q, c1, c2);
+            if (staged) {
+                QS_LAUNCH_CHECK();
+                continue;
             }
         }
         const InsertPlan plan = make_insert_plan(bits);

@@ -83,6 +83,37 @@ def test_multi_swap(qs, prec, density):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_swaps_staged_through_lds(qs, prec):
+    """Pairs that involve a bit inside a 128-byte line go through the
+    LDS-staged tile kernel once the register holds a whole tile: single and
+    multiple pairs, low-low, low-high, and a density matrix whose pairs are
+    doubled onto the column bits."""
+    rng = np.random.default_rng(19)
+    N = 14
+    psi = synth.random_state(rng, 1 << N)
+    cases = [([0], [13]), ([0], [1]), ([3], [13]), ([2], [9]), ([0, 1, 2], [13, 12, 11]),
+             ([0, 5, 9], [3, 12, 1]), ([1, 8], [11, 2]), ([0, 1, 2, 3], [10, 11, 12, 13])]
+    for a, b in cases:
+        banner(f"staged swaps {a}<->{b} N={N} {prec}")
+        q = qs.Qureg(N, precision=prec).set_amps(psi)
+        q.apply_multi_swap(a, b)
+        want = psi.copy()
+        for x, y in zip(a, b):
+            want = oracle.apply_swap(want, x, y)
+        assert amp_err(q.get_amps(), want) < TOL[prec]
+    Nd = 7
+    rho = _mixed_state(rng, Nd)
+    for a, b in (([0], [6]), ([1, 0], [5, 3]), ([2], [3])):
+        banner(f"staged density swaps {a}<->{b} N={Nd} {prec}")
+        q = qs.Qureg(Nd, density=True, precision=prec).set_amps(rho)
+        q.apply_multi_swap(a, b)
+        want = rho.copy()
+        for x, y in zip(a, b):
+            want = oracle.dm_apply_swap(want, x, y)
+        assert amp_err(q.get_amps(), want) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_pauli_tensor(qs, prec):
     N = 8
     rng = np.random.default_rng(14)
