@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for hardware-counter collection: one torch copy of 2 GiB "
                          "(the calibration kernel of known traffic), then one application of the "
-                         "28-qubit circuit compiled at --probe-fuse-k in --probe-precision")
+                         "28-qubit circuit (the 34-qubit one with --workload sv34) compiled at "
+                         "--probe-fuse-k in --probe-precision")
     ap.add_argument("--probe-fuse-k", type=int, default=12)
     ap.add_argument("--probe-precision", default="c64", choices=["c64", "c128"])
     ap.add_argument("--workload", default="circuit28", choices=["circuit28", "density14", "batch512", "sv34"],
@@ -172,7 +173,11 @@ def pmc_probe(args):
     dst.copy_(src)                      # reads 2 GiB, writes 2 GiB
     torch.cuda.synchronize()
     del src, dst
-    ops = synth.config2_circuit(num_qubits=n, num_gates=args.gates)
+    if args.workload == "sv34":
+        n = 34
+        ops = synth.config5_circuit()
+    else:
+        ops = synth.config2_circuit(num_qubits=n, num_gates=args.gates)
     q = qs.Qureg(n, precision=args.probe_precision).init_hashed(11)
     circ = qs.Circuit(n, ops).compile(args.probe_fuse_k, args.probe_precision)
     circ.apply(q)
