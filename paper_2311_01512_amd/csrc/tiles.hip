@@ -310,6 +310,15 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
     p.phases.clear();
     p.rops.clear();
     p.tmats.clear();
+    // Gadgets run as cos(theta) (1 + i tan(theta) eta P): the real factors
+    // cos(theta) of the step multiply every amplitude alike, so they are
+    // collected in `scale` and folded into one uncontrolled matrix of the step
+    // (or applied by a scaling operator at its end).  A factored gadget can
+    // grow an amplitude by up to 1 + |tan(theta)|; gadgets with |cos| < 1/64
+    // keep the unfactored form, as do all once the step's growth bound would
+    // pass 2^64.
+    double scale = 1.0, growth = 1.0;
+    std::vector<std::pair<size_t, size_t>> mat_range;   // tmats entries of each operator
     // A phase takes, in order, every remaining member that fits it and shares
     // no qubit with a remaining member it jumps over.
     std::vector<size_t> remaining(members.size());
@@ -379,6 +388,7 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
             const size_t m = chosen[ci];
             const CircOp *op = members[m];
             const Need &n = needs[m];
+            const size_t mat0 = p.tmats.size();
             ROp ro{};
             if (op->gadget) {
                 uint32_t f = n.flip, fu = 0;
@@ -390,7 +400,6 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
                     f ^= r[b];
                     fu |= 1u << b;
                 }
-                ro.code = 8 + (int)fu;
                 ro.yz = n.yz;
                 uint32_t ym = 0;
                 for (int b = 0; b < 64; b++)
@@ -399,11 +408,29 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
                 for (int b = 0; b < kRegBits; b++) ro.gy |= (uint32_t)(__builtin_popcount(r[b] & ym) & 1) << b;
                 const cd c = cd(0, std::sin(op->theta)) * eta[n.ny & 3];
                 const double partner = (__builtin_popcountll(n.x & n.yz) & 1) ? -1.0 : 1.0;
-                ro.cs = std::cos(op->theta);
-                ro.cre = c.real();
-                ro.cim = c.imag();
-                ro.pre = partner * c.real();
-                ro.pim = partner * c.imag();
+                const double cs = std::cos(op->theta);
+                const double tn = std::fabs(std::tan(op->theta));
+                if (std::fabs(cs) >= 1.0 / 64 && growth * (1.0 + tn) <= 0x1p64) {
+                    // c / cos(theta) = i tan(theta) eta: imaginary for an even
+                    // number of Y (codes 24+), real for an odd one (40+)
+                    const bool im = (n.ny & 1) == 0;
+                    const double k = (im ? c.imag() : c.real()) / cs;
+                    ro.code = (im ? 24 : 40) + (int)fu;
+                    ro.cs = 1.0;
+                    ro.cre = k;
+                    ro.cim = 0.0;
+                    ro.pre = partner * k;
+                    ro.pim = 0.0;
+                    scale *= cs;
+                    growth *= 1.0 + tn;
+                } else {
+                    ro.code = 8 + (int)fu;
+                    ro.cs = cs;
+                    ro.cre = c.real();
+                    ro.cim = c.imag();
+                    ro.pre = partner * c.real();
+                    ro.pim = partner * c.imag();
+                }
                 ro.fcs = (float)ro.cs;
                 ro.fcre = (float)ro.cre;
                 ro.fcim = (float)ro.cim;
@@ -463,8 +490,33 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
                 }
             }
             p.rops.push_back(ro);
+            mat_range.emplace_back(mat0, p.tmats.size());
         }
         p.phases.push_back(ph);
+    }
+    if (scale != 1.0) {
+        // an uncontrolled dense, sparse or matrix-core operator takes the
+        // factor in its matrix (every such form is linear in the matrix)
+        // (FP64 register matrices first; matrix-core coefficients are FP32)
+        bool folded = false;
+        for (int pass = 0; pass < 2 && !folded; pass++)
+            for (size_t i = 0; i < p.rops.size() && !folded; i++) {
+                const ROp &ro = p.rops[i];
+                const bool reg = (ro.code >= 1 && ro.code <= 7) || ro.code >= 64;
+                const bool core = ro.code >= 32 && ro.code <= 38 && ro.nc == 0;
+                if ((pass == 0 ? reg : core) && mat_range[i].second > mat_range[i].first) {
+                    for (size_t k = mat_range[i].first; k < mat_range[i].second; k++) p.tmats[k] *= scale;
+                    folded = true;
+                }
+            }
+        if (!folded) {
+            ROp ro{};
+            ro.code = 16;
+            ro.cs = scale;
+            ro.fcs = (float)scale;
+            p.rops.push_back(ro);
+            p.phases.back().num_ops++;
+        }
     }
     p.members = (int)members.size();
 }
@@ -694,6 +746,64 @@ __device__ __forceinline__ void reg_gadget(C2<R> (&x)[kRegs], const ROp &op, uin
     }
 }
 
+// Gadget with cos(theta) factored out into the step's scale: with
+// s = this thread's sign times the register parity, k the ratio
+// c / cos(theta) as a real number (the imaginary part when IM), u = i (IM)
+// or 1:
+//   pair:      x0 <- x0 + s kp u x1,  x1 <- x1 + s kc u x0
+//   diagonal:  x <- x + s kc i x      (FU = 0, Z only: IM)
+// one FMA per real component instead of a complex product.
+template <typename R, int FU, bool IM>
+__device__ __forceinline__ void reg_gadget_f(C2<R> (&x)[kRegs], const ROp &op, uint32_t tau, uint64_t base)
+{
+    const uint32_t st = (uint32_t)(__popcll(base & op.yz) + __popc(tau & op.yzm)) & 1u;
+    R kc, kp;
+    if constexpr (std::is_same<R, float>::value) {
+        kc = op.fcre;
+        kp = op.fpre;
+    } else {
+        kc = op.cre;
+        kp = op.pre;
+    }
+    const R a = st ? -kp : kp, b = st ? -kc : kc;
+    if constexpr (FU == 0) {
+#pragma unroll
+        for (int u = 0; u < kRegs; u++) {
+            const R k = (__popc((uint32_t)u & op.gy) & 1) ? -b : b;
+            const C2<R> v = x[u];
+            x[u] = mk<R>(fma(-k, v.y, v.x), fma(k, v.x, v.y));
+        }
+    } else {
+        constexpr int HB = 31 - __builtin_clz((unsigned)FU);
+#pragma unroll
+        for (int u0 = 0; u0 < kRegs; u0++) {
+            if ((u0 >> HB) & 1) continue;
+            const int u1 = u0 ^ FU;
+            const bool neg = __popc((uint32_t)u0 & op.gy) & 1;
+            const R k0 = neg ? -a : a, k1 = neg ? -b : b;
+            const C2<R> x0 = x[u0], x1 = x[u1];
+            if constexpr (IM) {
+                x[u0] = mk<R>(fma(-k0, x1.y, x0.x), fma(k0, x1.x, x0.y));
+                x[u1] = mk<R>(fma(-k1, x0.y, x1.x), fma(k1, x0.x, x1.y));
+            } else {
+                x[u0] = mk<R>(fma(k0, x1.x, x0.x), fma(k0, x1.y, x0.y));
+                x[u1] = mk<R>(fma(k1, x0.x, x1.x), fma(k1, x0.y, x1.y));
+            }
+        }
+    }
+}
+
+// The step's collected gadget factors, when no matrix of the step took them.
+template <typename R>
+__device__ __forceinline__ void reg_scale(C2<R> (&x)[kRegs], const ROp &op)
+{
+    R f;
+    if constexpr (std::is_same<R, float>::value) f = op.fcs;
+    else f = op.cs;
+#pragma unroll
+    for (int u = 0; u < kRegs; u++) x[u] = mk<R>(f * x[u].x, f * x[u].y);
+}
+
 // Dense gate on the FP32 matrix cores.  The wavefront's 64 lanes hold 16
 // groups: lane L has member g = L / 16 of group L % 16 (g's bits are the lane
 // coordinates), and for RM != 0 further members in registers u0 | rho.  Per
@@ -763,6 +873,22 @@ __device__ __forceinline__ void apply_reg_op(C2<R> (&x)[kRegs], const ROp &op, u
     case 13: reg_gadget<R, 5>(x, op, tau, base); break;
     case 14: reg_gadget<R, 6>(x, op, tau, base); break;
     case 15: reg_gadget<R, 7>(x, op, tau, base); break;
+    case 16: reg_scale<R>(x, op); break;
+    case 24: reg_gadget_f<R, 0, true>(x, op, tau, base); break;
+    case 25: reg_gadget_f<R, 1, true>(x, op, tau, base); break;
+    case 26: reg_gadget_f<R, 2, true>(x, op, tau, base); break;
+    case 27: reg_gadget_f<R, 3, true>(x, op, tau, base); break;
+    case 28: reg_gadget_f<R, 4, true>(x, op, tau, base); break;
+    case 29: reg_gadget_f<R, 5, true>(x, op, tau, base); break;
+    case 30: reg_gadget_f<R, 6, true>(x, op, tau, base); break;
+    case 31: reg_gadget_f<R, 7, true>(x, op, tau, base); break;
+    case 41: reg_gadget_f<R, 1, false>(x, op, tau, base); break;
+    case 42: reg_gadget_f<R, 2, false>(x, op, tau, base); break;
+    case 43: reg_gadget_f<R, 3, false>(x, op, tau, base); break;
+    case 44: reg_gadget_f<R, 4, false>(x, op, tau, base); break;
+    case 45: reg_gadget_f<R, 5, false>(x, op, tau, base); break;
+    case 46: reg_gadget_f<R, 6, false>(x, op, tau, base); break;
+    case 47: reg_gadget_f<R, 7, false>(x, op, tau, base); break;
     case 17: reg_dense<R, 1, true>(x, op, tau, base, m); break;
     case 18: reg_dense<R, 2, true>(x, op, tau, base, m); break;
     case 19: reg_dense<R, 3, true>(x, op, tau, base, m); break;
