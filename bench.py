@@ -268,6 +268,44 @@ def bench_special(q, torch, amp_bytes, reps=3):
     return res
 
 
+def bench_reductions(q, torch, amp_bytes, reps=3):
+    """The read-only calculations on a statevector or density qureg: average
+    ms per call (each call ends with the scalar copied to the host) and GB/s
+    of the amplitudes the kernel must read.  Statevector: norm (every
+    amplitude), P(qubit N-1 = 0) (half), a 20-term Pauli sum (one pass per
+    distinct X/Y flip mask among the terms).  Density matrix: trace and
+    P(qubit = 0) (the 2^N diagonal entries), purity (every entry), the
+    20-term Pauli sum (2^N entries per term)."""
+    import numpy as np
+    n = q.num_qubits
+    rng = np.random.default_rng(20)
+    codes = rng.integers(0, 4, size=(20, n)).astype(np.int32)
+    coeffs = rng.standard_normal(20)
+    masks = {int(sum(1 << k for k in range(n) if c[k] in (1, 2))) for c in codes}
+    if q.density:
+        calls = [("trace", lambda: q.trace(), 1 << n),
+                 ("prob_of_outcome", lambda: q.prob_of_outcome(0, 0), 1 << n),
+                 ("purity", lambda: q.purity(), q.num_amps),
+                 ("expec_pauli_sum_20", lambda: q.expec_pauli_sum(codes, coeffs), 20 << n)]
+    else:
+        calls = [("total_prob", lambda: q.total_prob(), q.num_amps),
+                 ("prob_of_outcome", lambda: q.prob_of_outcome(n - 1, 0), q.num_amps // 2),
+                 ("expec_pauli_sum_20", lambda: q.expec_pauli_sum(codes, coeffs), len(masks) * q.num_amps)]
+    res = {}
+    for name, fn, amps in calls:
+        fn()                                   # untimed first call
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(q.stream)
+        for _ in range(reps):
+            fn()
+        b.record(q.stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / reps
+        byts = amp_bytes * amps
+        res[name] = {"ms": ms, "GBps": byts / (ms * 1e-3) / 1e9, "hbm_frac": byts / (ms * 1e-3) / 8e12}
+    return res
+
+
 def bench_density(args, torch, qs, synth):
     """14-qubit density matrix (Choi vector of 2^28 amplitudes): 300 ops of
     Haar unitaries, depolarising, damping and random Kraus maps applied as
@@ -310,7 +348,8 @@ def bench_density(args, torch, qs, synth):
                      "roofline": roofline(kinds, ab, 2 * n),
                      "per_kind": per_kernel_table(kinds, ab),
                      "channels": bench_channels(q, torch, ab),
-                     "special_ops": bench_special(q, torch, ab)}
+                     "special_ops": bench_special(q, torch, ab),
+                     "reductions": bench_reductions(q, torch, ab)}
         if prec == "c128":
             # reference result of the plain FP64 path, from |0><0|, one application
             q.init_zero().run_ops(ops)
@@ -498,6 +537,8 @@ def main():
         "speedup_fused_c64_vs_plain_c128": t128 / t64,
         "special_ops_c128": bench_special(q128, torch, 16),
         "special_ops_c64": bench_special(q64, torch, 8),
+        "reductions_c128": bench_reductions(q128, torch, 16),
+        "reductions_c64": bench_reductions(q64, torch, 8),
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_seconds)

@@ -44,7 +44,14 @@ __global__ __launch_bounds__(256) void k_reduce(F f, uint64_t n, double *__restr
 {
     double re = 0.0, im = 0.0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) f(i, re, im);
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // eight elements per round, so that their loads are in flight together
+    // (the accumulations keep the index order: the sum stays deterministic)
+    for (; i + 7 * stride < n; i += 8 * stride) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) f(i + k * stride, re, im);
+    }
+    for (; i < n; i += stride) f(i, re, im);
     block_sum2(re, im);
     if (threadIdx.x == 0) {
         partials[2 * blockIdx.x] = re;
