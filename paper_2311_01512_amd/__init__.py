@@ -19,4 +19,7 @@ def __getattr__(name):
     if name == "Batch":
         from .batch import Batch
         return Batch
+    if name in ("BatchEnergy", "energies"):
+        from . import batch
+        return getattr(batch, name)
     raise AttributeError(name)

@@ -1,7 +1,9 @@
 """Batch: many parametrised circuits of uneven size evaluated together on
 the GPU (energies <psi(theta)|H|psi(theta)> and adjoint gradients), driven
-through the qs_batch_* C entry points."""
+through the qs_batch_* C entry points, and `energies`, the same as a
+differentiable torch function of the parameters."""
 import numpy as np
+import torch
 
 from . import native as N
 
@@ -47,6 +49,10 @@ class Batch:
         """params: concatenated parameter vectors.  Returns (energies, grads)."""
         return N.qs_batch_run(self._b, params, len(self.num_qubits), sum(self.num_params), grads)
 
+    def param_owner(self):
+        """Circuit index of every parameter of the concatenated vector."""
+        return np.repeat(np.arange(len(self.num_params)), self.num_params)
+
     def state(self, circuit):
         return N.qs_batch_get_state(self._b, circuit, self.num_qubits[circuit])
 
@@ -63,3 +69,34 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class BatchEnergy(torch.autograd.Function):
+    """Energies E_c(theta) of every circuit of a compiled Batch as a function
+    of the concatenated parameter vector.  The forward pass runs the batch
+    with the adjoint sweep (one GPU run gives the energies and every dE_c /
+    dtheta_p) and keeps the gradients; the backward pass returns
+    grad_E[c(p)] * dE_c(p) / dtheta_p, c(p) being the circuit that owns
+    parameter p (each parameter belongs to exactly one circuit)."""
+
+    @staticmethod
+    def forward(ctx, params, batch):
+        if not batch.compiled:
+            raise RuntimeError("compile the batch first")
+        p = params.detach().to(device="cpu", dtype=torch.float64).contiguous().numpy()
+        e, g = batch.run(p, grads=True)
+        ctx.save_for_backward(torch.from_numpy(np.ascontiguousarray(g)))
+        ctx.owner = torch.from_numpy(batch.param_owner())
+        ctx.device, ctx.dtype = params.device, params.dtype
+        return torch.from_numpy(np.ascontiguousarray(e)).to(device=params.device)
+
+    @staticmethod
+    def backward(ctx, grad_e):
+        (g,) = ctx.saved_tensors
+        w = grad_e.detach().to(device="cpu", dtype=torch.float64)[ctx.owner]
+        return (w * g).to(device=ctx.device, dtype=ctx.dtype), None
+
+
+def energies(batch, params):
+    """Differentiable energies of a compiled Batch (see BatchEnergy)."""
+    return BatchEnergy.apply(params, batch)
