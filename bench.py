@@ -47,14 +47,23 @@ def parse():
                          "--probe-fuse-k in --probe-precision")
     ap.add_argument("--probe-fuse-k", type=int, default=12)
     ap.add_argument("--probe-precision", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--probe-specialize", action="store_true",
+                    help="compile the probe circuit's tile steps into a kernel each first")
+    ap.add_argument("--no-specialize", action="store_true",
+                    help="keep the generic tile-step kernel (no run-time compilation)")
     ap.add_argument("--workload", default="circuit28", choices=["circuit28", "density14", "batch512", "sv34"],
                     help="circuit28 (default, the headline): 28-qubit 500-gate circuit; density14: 14-qubit "
                          "density matrix; batch512: 512 circuits with energies and gradients; sv34: 34 qubits")
     return ap.parse_args()
 
 
-def kernel_name(info, real):
+SPECIALIZED_TILE = "qs_step_* (tile steps compiled per step at run time)"
+
+
+def kernel_name(info, real, specialized=False):
     k = info["kernel"]
+    if k == "tile" and specialized:
+        return f"{SPECIALIZED_TILE}<{real}>"
     if k == "gadget_pairs":
         return f"k_gadget_pairs<{real}>"
     if k == "gadget_diag":
@@ -77,9 +86,10 @@ def measured_traffic(kernel, n):
     rec = json.load(open(path)).get(f"{kernel}@{n}q")
     if not rec:
         return None
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest()[:len(rec["sha256_prefix"])] != rec["sha256_prefix"]:
-        return None
+    for name, prefix in rec["sources"].items():
+        src = open(os.path.join(ROOT, name), "rb").read()
+        if hashlib.sha256(src).hexdigest()[:len(prefix)] != prefix:
+            return None
     return rec["bytes_per_launch"]
 
 
@@ -111,7 +121,7 @@ def time_passes(circ, q, torch):
     torch.cuda.synchronize()
     out = {}
     for info, (a, b) in zip(infos, ev):
-        name = kernel_name(info, real)
+        name = kernel_name(info, real, circ.specialized > 0)
         amps = 1 << (n - info["num_ctrls"])
         if info["kernel"] == "tile":
             amps = 1 << n          # one read and one write of the whole state per step
@@ -180,10 +190,13 @@ def pmc_probe(args):
         ops = synth.config2_circuit(num_qubits=n, num_gates=args.gates)
     q = qs.Qureg(n, precision=args.probe_precision).init_hashed(11)
     circ = qs.Circuit(n, ops).compile(args.probe_fuse_k, args.probe_precision)
+    if args.probe_specialize:
+        circ.specialize()
     circ.apply(q)
     q.sync()
     print(json.dumps({"pmc_probe": "done", "gates": len(ops), "num_qubits": n,
-                      "fuse_k": args.probe_fuse_k, "precision": args.probe_precision}), flush=True)
+                      "fuse_k": args.probe_fuse_k, "precision": args.probe_precision,
+                      "specialized": circ.specialized}), flush=True)
 
 
 def base_line(metric_value, unit, steps, warmup, ms, dtype, workload, extra):
@@ -201,12 +214,33 @@ def dm_op_kind(op):
     return ("dm_unitary" if op["op"] == "unitary" else "kraus") + f"_{k}q"
 
 
-def path_text(k):
+def path_text(k, specialized=False):
     if k == 0:
         return "one pass per operator"
     if k <= 6:
         return f"operators fused into dense blocks of <= {k} qubits (FP32 MFMA for 4-6 qubit blocks)"
-    return f"tile steps of 2^{k} amplitudes: each step applies its operators on chip in one HBM pass"
+    return (f"tile steps of 2^{k} amplitudes: each step applies its operators on chip in one HBM pass"
+            + ("; each step compiled into a kernel of its own at run time" if specialized else ""))
+
+
+def try_specialize(circ, q, k, torch, reps=2, disabled=False):
+    """For a circuit compiled into tile steps: times the generic tile kernel,
+    compiles each step into a kernel of its own, times that, and keeps the
+    faster form (recompiling drops the specialised one).  Overwrites the
+    qureg's state.  Returns a record of both timings, or None."""
+    if k < 8 or disabled:
+        return None
+    generic = time_steps(circ, q, reps, torch)
+    t0 = time.perf_counter()
+    nk = circ.specialize()
+    compile_s = time.perf_counter() - t0
+    circ.apply(q)                       # first launch of each module
+    spec = time_steps(circ, q, reps, torch)
+    rec = {"kernels": nk, "compile_s": compile_s, "generic_ms": generic * 1e3, "specialized_ms": spec * 1e3,
+           "used": spec < generic}
+    if not rec["used"]:
+        circ.compile(*circ.compiled_for)
+    return rec
 
 
 def bench_channels(q, torch, amp_bytes):
@@ -361,6 +395,7 @@ def bench_density(args, torch, qs, synth):
     circ = qs.Circuit(n, ops, density=True)
     cands = tuple(int(x) for x in args.fuse_candidates.split(","))
     best_k, tune_ms = circ.autotune(q, cands)
+    spec = try_specialize(circ, q, best_k, torch, disabled=args.no_specialize)
     q.init_zero()
     for _ in range(args.warmup):
         circ.apply(q)
@@ -379,8 +414,8 @@ def bench_density(args, torch, qs, synth):
     tr, pur = q.trace(), q.purity()
     st = circ.stats()
     fused = {"value": logical / step_s, "ms_per_step": step_s * 1e3, "fuse_k": best_k,
-             "autotune_ms": {str(k): v for k, v in tune_ms.items()}, "passes": st["num_passes"],
-             "max_amp_err_vs_c128": err, "per_kernel": per_kernel_table(kinds, 8),
+             "autotune_ms": {str(k): v for k, v in tune_ms.items()}, "specialization": spec,
+             "passes": st["num_passes"], "max_amp_err_vs_c128": err, "per_kernel": per_kernel_table(kinds, 8),
              "partial_trace_ms": ta.elapsed_time(tb),
              "trace": [tr.real, tr.imag], "purity": [pur.real, pur.imag],
              "reduced_trace": red.trace().real, "reduced_purity": red.purity().real}
@@ -391,7 +426,7 @@ def bench_density(args, torch, qs, synth):
                      {"roofline": roofline(kinds, 8, 2 * n), "fused_c64": fused,
                       "plain_c128": out["c128"], "plain_c64": out["c64"],
                       "speedup_fused_c64_vs_plain_c128": out["c128"]["ms_per_step"] / fused["ms_per_step"]})
-    line["config"]["path"] = "complex64 density circuit, " + path_text(best_k)
+    line["config"]["path"] = "complex64 density circuit, " + path_text(best_k, circ.specialized > 0)
     del q, red
     return line
 
@@ -491,6 +526,7 @@ def main():
     fused = qs.Circuit(n, ops)
     cands = tuple(int(x) for x in args.fuse_candidates.split(","))
     best_k, tune_ms = fused.autotune(q64, cands)
+    spec = try_specialize(fused, q64, best_k, torch, disabled=args.no_specialize)
     # plain complex128, one pass per gate
     plain = qs.Circuit(n, ops).compile(0, "c128")
     q128 = qs.Qureg(n, precision="c128")
@@ -526,10 +562,10 @@ def main():
         "config": {"workload": f"{n}-qubit statevector, {len(ops)}-gate random circuit (Haar 1q, "
                                "2-target Haar with 0-3 controls, Pauli gadgets of weight 1-N)",
                    "num_qubits": n, "gates": len(ops),
-                   "path": f"complex64, {path_text(best_k)} (fusion width autotuned)"},
+                   "path": f"complex64, {path_text(best_k, fused.specialized > 0)} (fusion width autotuned)"},
         "roofline": roofline(kinds64, 8, n),
         "fused_c64": {"value": logical / t64, "ms_per_step": t64 * 1e3, "fuse_k": best_k,
-                      "autotune_ms": {str(k): v for k, v in tune_ms.items()},
+                      "autotune_ms": {str(k): v for k, v in tune_ms.items()}, "specialization": spec,
                       "passes": st["num_passes"], "passes_by_width": st["passes_by_width"],
                       "max_amp_err_vs_c128": err, "per_kernel": per_kernel_table(kinds64, 8)},
         "plain_c128": {"value": logical / t128, "ms_per_step": t128 * 1e3, "passes": len(ops),

@@ -318,6 +318,24 @@ int qs_circuit_add_kraus_map(qs_circuit *c, const int *targs, int num_targs, con
  * layout.  QS_E_ARG for a fuse_k outside 0, 2..6, 8..13 or beyond the
  * device's tile limit. */
 int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision);
+
+/*
+ * Run-time specialisation of a compiled circuit's tile steps: each step
+ * becomes a kernel of its own, generated as HIP source with the step's
+ * register phases and operators as compile-time constants and compiled for
+ * the current device by `$ROCM_PATH/llvm/bin/clang++` (default /opt/rocm),
+ * run as up to eight child processes with sources written to a temporary
+ * directory under $TMPDIR (default /tmp) that is removed afterwards (seconds
+ * for hundreds of operators; code objects are cached per source for the
+ * process).  Applying the circuit then
+ * launches these kernels; results equal those of the generic tile kernel.
+ * *num_kernels (may be NULL) receives the number of specialised steps (0 for
+ * a circuit without tile steps).  Recompiling or destroying the circuit
+ * releases them.  Errors: QS_E_PRECOND if not compiled, QS_E_HIP if the
+ * run-time compilation or module load fails (the circuit keeps the generic
+ * kernels).
+ */
+int qs_circuit_specialize(qs_circuit *c, int *num_kernels);
 /* Pass statistics of the compiled circuit; any pointer may be NULL.
  * logical_updates: amplitude updates under the plain per-gate accounting
  * (2^(N-s) per s-controlled gate, 2^N per gadget) of the recorded ops;

@@ -10,6 +10,7 @@ class Circuit:
         self.density = bool(density)
         self._c = (N.qs_circuit_create_density if self.density else N.qs_circuit_create)(self.num_qubits)
         self.compiled_for = None
+        self.specialized = 0
         for op in ops:
             self.add(op)
 
@@ -30,12 +31,22 @@ class Circuit:
         else:
             raise ValueError(f"unknown op {kind}")
         self.compiled_for = None
+        self.specialized = 0
         return self
 
     def compile(self, fuse_k=0, precision="c64"):
         N.qs_circuit_compile(self._c, int(fuse_k), N.QS_C64 if precision == "c64" else N.QS_C128)
         self.compiled_for = (int(fuse_k), precision)
+        self.specialized = 0
         return self
+
+    def specialize(self):
+        """Compiles every tile step of the compiled circuit into a kernel of
+        its own at run time (the ROCm clang, run as child processes); returns
+        the number of such kernels.
+        Recompiling the circuit drops them."""
+        self.specialized = N.qs_circuit_specialize(self._c)
+        return self.specialized
 
     def stats(self):
         return N.qs_circuit_stats(self._c)
@@ -57,6 +68,7 @@ class Circuit:
         (best_k, {k: ms})."""
         best, ms = N.qs_circuit_autotune(qureg.handle, self._c, candidates)
         self.compiled_for = (best, qureg.precision)
+        self.specialized = 0
         return best, dict(zip(candidates, ms.tolist()))
 
     def close(self):

@@ -196,6 +196,7 @@ int qs_circuit_create_density(int num_qubits, qs_circuit **out)
 int qs_circuit_destroy(qs_circuit *c)
 {
     if (!c) return QS_OK;
+    release_specialized(c);
     if (c->dev) (void)hipFree(c->dev);
     delete c;
     return QS_OK;
@@ -312,6 +313,7 @@ int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision)
         return fail(QS_E_ARG, "fuse_k is 0, 2..6 (dense blocks) or 8.." + std::to_string(kTileDimMax) + " (tiles)");
     if (tiles && fuse_k > tile_dim_limit(precision))
         return fail(QS_E_ARG, "tile of 2^" + std::to_string(fuse_k) + " amplitudes exceeds the LDS of a block");
+    release_specialized(c);
     c->passes.clear();
     if (fuse_k == 0) {
         for (const auto &op : c->ops) c->passes.push_back(single_pass(op));

@@ -26,63 +26,6 @@ struct CircOp {
     }
 };
 
-// Tile steps.  A tile is the coset base ^ span(w_0..w_{d-1}) (reduced
-// echelon basis, coordinate k <-> w_k in ascending pivot order); element c
-// sits at base ^ (xor of w_k over the set bits k of c), and qubit b of
-// element c equals bit b of base ^ parity(c & m_b), m_b = sum_k (bit b of
-// w_k) << k.  Each thread of the block holds kRegs elements of the tile in
-// registers; which elements is the layout of a phase (RPhase), and every
-// operator of a phase only mixes elements held by one thread.
-constexpr int kRegBits = 3;
-constexpr int kRegs = 1 << kRegBits;
-constexpr int kTileDimMax = kRegBits + 10;   // 1024 threads per block
-
-// Thread t holds coordinates tau(t) ^ rho[u], u < kRegs: rho spans the
-// phase's register subspace (basis r_j, each with its own pivot bit), and
-// tau deposits the bits of t, in order, at the coordinates that are not
-// pivots.  In a phase with matrix-core operators (c4 >= 0) bits 4 and 5 of t
-// go to the lane coordinates c4 and c5 instead, and the other bits skip them.
-struct RPhase {
-    uint32_t rho[kRegs];
-    uint32_t lo[kRegBits + 2];      // (1 << q) - 1 for the pivots and lane coordinates, ascending
-    int nlo;                        // kRegBits, or kRegBits + 2 with lane coordinates
-    int c4, c5;
-    uint32_t pad_;
-    uint64_t yaddr[kRegs];          // index offset of rho[u] (xor of w_k)
-    uint64_t taddr[kTileDimMax];    // index offset of thread bit k
-    int first_op, num_ops;
-};
-
-// One operator of a phase, on register indices.
-//   code 1..7: dense gate whose targets are the register bits set in code
-//              (matrix bit i <-> i-th lowest of them); 17..23: the same with
-//              nc controls, control i set where bit cq[i] of base ^
-//              parity(tau & cm[i]) ^ bit i of qtab's nibble u is 1
-//   code 8:    diagonal Pauli gadget; code 9..15: gadget pairing register u
-//              with u ^ (code - 8).  Sign parity of element (t, u) is
-//              parity(base & yz) ^ parity(tau & yzm) ^ parity(u & gy); the
-//              partner's sign is folded into (pre, pim).
-//   code 32..38: dense gate on the matrix cores (complex64): targets on the
-//              lane coordinates c4, c5 and the register bits set in code - 32;
-//              mat indexes its per-lane MFMA coefficients; controls as above.
-//   code 64 + 4 UM + s: uncontrolled gate on register bits UM (1 or 2 of
-//              them) whose matrix couples member j only with j ^ s (s = 0:
-//              diagonal).
-struct ROp {
-    int code;
-    int nc;
-    int cq[4];
-    uint32_t cm[4];
-    uint64_t qtab;
-    uint64_t yz;
-    uint32_t yzm, gy;
-    int mat;                        // first entry of its matrix in the table
-    uint32_t hsel;                  // matrix-core gate: 2 bits per register, rho[u] at (c4, c5)
-    double cs, cre, cim;            // gadget: cos(theta), i sin(theta) i^{#Y}
-    double pre, pim;                // (cre, cim) times (-1)^parity(x & yz)
-    float fcs, fcre, fcim, fpre, fpim;   // the same in FP32 for complex64 tiles
-};
-
 struct Pass {
     bool gadget;
     std::vector<int> ctrls, sorted_targs;
@@ -101,6 +44,9 @@ struct Pass {
     std::vector<RPhase> phases;
     std::vector<ROp> rops;
     std::vector<cd> tmats;            // dense matrices of the step, concatenated
+    // kernel specialised for this step at run time (jit.hip), or null
+    void *jit_fn = nullptr;
+    unsigned jit_grid = 0;            // its resident-block grid
 };
 
 // LDS tile engine (tiles.hip).
@@ -112,6 +58,11 @@ void plan_tiles(qs_circuit *c, int T, int precision);
 size_t tile_pass_bytes(const Pass &p, int precision);
 void pack_tile_pass(const Pass &p, int precision, void *out);
 int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev);
+// Offset of a tile pass's matrix table within its device tables.
+size_t tile_mats_offset(const Pass &p);
+// Run-time specialisation of a compiled circuit's tile steps (jit.hip).
+int specialize_tiles(qs_circuit *c, int *num_kernels);
+void release_specialized(qs_circuit *c);
 
 Pass single_pass(const CircOp &op);
 
@@ -129,4 +80,5 @@ struct qs_circuit {
     void *dev = nullptr;
     size_t dev_bytes = 0;
     int device = -1;
+    std::vector<void *> jit_modules;   // modules of the specialised tile-step kernels
 };

@@ -11,54 +11,9 @@
 #include <vector>
 
 #include "../../include/qsim.h"
+#include "dev_core.hpp"
 
 namespace qs {
-
-// ---- amplitudes --------------------------------------------------------------
-
-template <typename R> struct cplx_t;
-template <> struct cplx_t<float> { using type = float2; };
-template <> struct cplx_t<double> { using type = double2; };
-template <typename R> using C2 = typename cplx_t<R>::type;
-
-template <typename R> __device__ __forceinline__ C2<R> mk(R x, R y) { C2<R> c; c.x = x; c.y = y; return c; }
-
-// acc += m * v (complex)
-template <typename R>
-__device__ __forceinline__ void cmac(C2<R> &acc, const C2<R> m, const C2<R> v)
-{
-    acc.x = fma(m.x, v.x, acc.x);
-    acc.x = fma(-m.y, v.y, acc.x);
-    acc.y = fma(m.x, v.y, acc.y);
-    acc.y = fma(m.y, v.x, acc.y);
-}
-
-template <typename R>
-__device__ __forceinline__ C2<R> cmul(const C2<R> a, const C2<R> b)
-{
-    return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-// ---- bit-index algebra (Alg. "bit_twiddles") ------------------------------------
-
-constexpr int kMaxInsert = 24;   // qubits spliced into a loop index by one launch
-
-// Splices zero bits into an index at ascending positions q_0 < q_1 < ...
-// (insertBits of the paper with b = 0), stored as the masks (1 << q_k) - 1.
-struct InsertPlan {
-    int n;
-    uint64_t low[kMaxInsert];
-};
-
-__device__ __forceinline__ uint64_t insert_zeros(uint64_t g, const InsertPlan &p)
-{
-#pragma unroll 4
-    for (int k = 0; k < p.n; k++) {
-        const uint64_t lo = p.low[k];
-        g = (g & lo) | ((g & ~lo) << 1);
-    }
-    return g;
-}
 
 inline InsertPlan make_insert_plan(std::vector<int> qubits)
 {

@@ -80,6 +80,7 @@ _SIGS = {
     "qs_circuit_add_unitary": [_P, _P, _I, _P, _I, _P],
     "qs_circuit_add_pauli_gadget": [_P, _P, _P, _I, _D],
     "qs_circuit_compile": [_P, _I, _I],
+    "qs_circuit_specialize": [_P, C.POINTER(C.c_int)],
     "qs_circuit_stats": [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_uint64), C.POINTER(C.c_int)],
     "qs_apply_circuit": [_P, _P],
     "qs_apply_circuit_passes": [_P, _P, _I, _I],
@@ -362,6 +363,12 @@ def qs_circuit_add_pauli_gadget(c, targs, paulis, theta):
 
 def qs_circuit_compile(c, fuse_k, precision):
     check(lib.qs_circuit_compile(c, fuse_k, precision), "qs_circuit_compile")
+
+
+def qs_circuit_specialize(c):
+    n = C.c_int()
+    check(lib.qs_circuit_specialize(c, C.byref(n)), "qs_circuit_specialize")
+    return n.value
 
 
 def qs_circuit_stats(c):

@@ -1,0 +1,127 @@
+"""Tile steps specialised at run time (each step compiled into a kernel of
+its own by the ROCm clang): the same results as the generic tile kernel, bit
+for bit, and parity with the FP64 oracle; the on-disk code-object cache."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import TOL, amp_err, banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qs():
+    import paper_2311_01512_amd as pkg
+    return pkg
+
+
+@pytest.mark.parametrize("prec,k", [("c64", 12), ("c128", 11), ("c64", 10)])
+def test_specialized_equals_generic_and_oracle(qs, prec, k):
+    banner(f"specialised tiles {prec} k={k}")
+    N = 14
+    ops = synth.config2_circuit(num_qubits=N, num_gates=160)
+    rng = np.random.default_rng(71)
+    psi = synth.random_state(rng, 1 << N)
+    c = qs.Circuit(N, ops).compile(k, prec)
+    q = qs.Qureg(N, precision=prec).set_amps(psi)
+    c.apply(q)
+    generic = q.get_amps()
+    nk = c.specialize()
+    assert nk > 0
+    q.set_amps(psi)
+    c.apply(q)
+    special = q.get_amps()
+    assert np.array_equal(special, generic)
+    assert amp_err(special, oracle.run_ops(psi.copy(), ops)) < TOL[prec]
+
+
+@pytest.mark.parametrize("N,k,prec,seed", [(24, 12, "c64", 11), (22, 10, "c64", 5), (20, 13, "c64", 11),
+                                           (24, 11, "c128", 11)])
+def test_every_specialized_pass_equals_generic(qs, N, k, prec, seed):
+    """Each step of a 500-gate circuit on a state with many tiles, applied by
+    its own kernel and by the generic one to the same input, bit for bit.
+    (Steps with controls on tile-base qubits once came out wrong when the
+    prefetch registers were left undefined after the last tile.)"""
+    banner(f"every specialised pass N={N} k={k} {prec} seed={seed}")
+    import torch
+    ops = synth.config2_circuit(num_qubits=N, num_gates=500, seed=seed)
+    cg = qs.Circuit(N, ops).compile(k, prec)
+    cs = qs.Circuit(N, ops).compile(k, prec)
+    assert cs.specialize() > 0
+    qg = qs.Qureg(N, precision=prec).init_hashed(7)
+    qx = qs.Qureg(N, precision=prec)
+    bad = []
+    for i in range(cg.stats()["num_passes"]):
+        qx.tensor.copy_(qg.tensor)
+        cg.apply_passes(qg, i, 1)
+        cs.apply_passes(qx, i, 1)
+        qx.sync()
+        qg.sync()
+        if not torch.equal(qg.tensor, qx.tensor):
+            bad.append(i)
+    assert bad == []
+
+
+def test_specialized_density_circuit(qs):
+    """A density circuit with Kraus maps as sparse and matrix-core operators."""
+    banner("specialised density circuit")
+    N = 7
+    ops, _ = synth.config3_circuit(num_qubits=N, num_ops=80)
+    rng = np.random.default_rng(72)
+    psi = synth.random_state(rng, 1 << N)
+    rho = np.outer(psi, psi.conj()).reshape(-1, order="F")
+    c = qs.Circuit(N, ops, density=True).compile(12, "c64")
+    q = qs.Qureg(N, density=True, precision="c64").set_amps(rho)
+    c.apply(q)
+    generic = q.get_amps()
+    c.specialize()
+    q.set_amps(rho)
+    c.apply(q)
+    assert np.array_equal(q.get_amps(), generic)
+    assert amp_err(q.get_amps(), oracle.run_ops(rho.copy(), ops, density=True)) < TOL["c64"]
+
+
+def test_recompile_drops_specialization(qs):
+    banner("recompile after specialise")
+    N = 12
+    ops = synth.config2_circuit(num_qubits=N, num_gates=60)
+    rng = np.random.default_rng(73)
+    psi = synth.random_state(rng, 1 << N)
+    c = qs.Circuit(N, ops).compile(11, "c64")
+    c.specialize()
+    c.compile(10, "c64")            # new passes: the specialised kernels are gone
+    q = qs.Qureg(N, precision="c64").set_amps(psi)
+    c.apply(q)
+    assert amp_err(q.get_amps(), oracle.run_ops(psi.copy(), ops)) < TOL["c64"]
+    assert qs.Circuit(N, ops).compile(0, "c64").specialize() == 0   # no tile steps
+
+
+def test_disk_cache(qs, tmp_path, monkeypatch):
+    """Code objects land in $QS_JIT_CACHE as files that start with their
+    whole compilation key; a second circuit with the same steps loads them."""
+    banner("specialised tiles: disk cache")
+    monkeypatch.setenv("QS_JIT_CACHE", str(tmp_path))
+    N = 13
+    ops = synth.config2_circuit(num_qubits=N, num_gates=70, seed=74)
+    rng = np.random.default_rng(74)
+    psi = synth.random_state(rng, 1 << N)
+    c = qs.Circuit(N, ops).compile(12, "c64")
+    q = qs.Qureg(N, precision="c64").set_amps(psi)
+    c.apply(q)
+    generic = q.get_amps()
+    assert c.specialize() > 0
+    files = sorted(os.listdir(tmp_path))
+    assert files and all(f.endswith(".co") for f in files)
+    for f in files:
+        blob = (tmp_path / f).read_bytes()
+        assert b"qs_step_" in blob.split(b"\0", 1)[0]      # the key holds the generated source
+    c2 = qs.Circuit(N, ops).compile(12, "c64")
+    assert c2.specialize() > 0
+    assert sorted(os.listdir(tmp_path)) == files
+    q.set_amps(psi)
+    c2.apply(q)
+    assert np.array_equal(q.get_amps(), generic)
