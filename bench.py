@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for hardware-counter collection: one torch copy of 2 GiB "
                          "(the calibration kernel of known traffic), then one application of the "
-                         "28-qubit circuit (the 34-qubit one with --workload sv34) compiled at "
+                         "28-qubit circuit (with --workload sv34 the 34-qubit one, with density14 the "
+                         "14-qubit density circuit) compiled at "
                          "--probe-fuse-k in --probe-precision")
     ap.add_argument("--probe-fuse-k", type=int, default=12)
     ap.add_argument("--probe-precision", default="c64", choices=["c64", "c128"])
@@ -75,15 +76,16 @@ def kernel_name(info, real, specialized=False):
     return f"k_gate<{real}, {info['num_targs']}>"
 
 
-def measured_traffic(kernel, n):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (profiles/traffic.json), or None when there is none or the
-    kernel's source changed since the counters were taken."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary (profiles/traffic.json), or None when there is
+    none or one of the kernel's sources changed since the counters were
+    taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path)).get(f"{kernel}@{n}q")
+    rec = json.load(open(path)).get(f"{kernel}@{workload}")
     if not rec:
         return None
     for name, prefix in rec["sources"].items():
@@ -140,18 +142,18 @@ def per_kernel_table(kinds, amp_bytes):
                 "TFLOPs": (v[3] / (v[1] * 1e-3) / 1e12) if v[3] else None} for k, v in kinds.items()}
 
 
-def roofline(kinds, amp_bytes, n):
+def roofline(kinds, amp_bytes, workload):
     name, (launches, ms, amps, flops) = max(kinds.items(), key=lambda kv: kv[1][1])
     avg_s = ms * 1e-3 / launches
     if name.startswith("k_dense_mfma<6>"):
         achieved = flops / launches / avg_s / 1e12
         return {"bound": "mfma", "achieved": achieved, "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / MFMA_F32_PEAK_TFLOPS, "traffic": measured_traffic(name, n),
+                "frac": achieved / MFMA_F32_PEAK_TFLOPS, "traffic": measured_traffic(name, workload),
                 "kernel": name, "avg_launch_ms": avg_s * 1e3, "flops_per_launch": flops / launches}
     bytes_per_launch = 2 * amp_bytes * amps / launches
     achieved = bytes_per_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, n),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, workload),
             "kernel": name, "avg_launch_ms": avg_s * 1e3, "bytes_per_launch": bytes_per_launch}
 
 
@@ -183,13 +185,17 @@ def pmc_probe(args):
     dst.copy_(src)                      # reads 2 GiB, writes 2 GiB
     torch.cuda.synchronize()
     del src, dst
+    density = args.workload == "density14"
     if args.workload == "sv34":
         n = 34
         ops = synth.config5_circuit()
+    elif density:
+        n = 14
+        ops, _ = synth.config3_circuit()
     else:
         ops = synth.config2_circuit(num_qubits=n, num_gates=args.gates)
-    q = qs.Qureg(n, precision=args.probe_precision).init_hashed(11)
-    circ = qs.Circuit(n, ops).compile(args.probe_fuse_k, args.probe_precision)
+    q = qs.Qureg(n, density=density, precision=args.probe_precision).init_hashed(11)
+    circ = qs.Circuit(n, ops, density=density).compile(args.probe_fuse_k, args.probe_precision)
     if args.probe_specialize:
         circ.specialize()
     circ.apply(q)
@@ -223,24 +229,14 @@ def path_text(k, specialized=False):
             + ("; each step compiled into a kernel of its own at run time" if specialized else ""))
 
 
-def try_specialize(circ, q, k, torch, reps=2, disabled=False):
-    """For a circuit compiled into tile steps: times the generic tile kernel,
-    compiles each step into a kernel of its own, times that, and keeps the
-    faster form (recompiling drops the specialised one).  Overwrites the
-    qureg's state.  Returns a record of both timings, or None."""
-    if k < 8 or disabled:
-        return None
-    generic = time_steps(circ, q, reps, torch)
-    t0 = time.perf_counter()
-    nk = circ.specialize()
-    compile_s = time.perf_counter() - t0
-    circ.apply(q)                       # first launch of each module
-    spec = time_steps(circ, q, reps, torch)
-    rec = {"kernels": nk, "compile_s": compile_s, "generic_ms": generic * 1e3, "specialized_ms": spec * 1e3,
-           "used": spec < generic}
-    if not rec["used"]:
-        circ.compile(*circ.compiled_for)
-    return rec
+def autotune(circ, q, cands, args):
+    """The library's autotuner over `cands`, with specialised tile steps as
+    further candidates unless --no-specialize; returns (best_k, generic ms by
+    k, specialised ms by k or None)."""
+    if args.no_specialize:
+        best_k, tune_ms = circ.autotune(q, cands)
+        return best_k, tune_ms, None
+    return circ.autotune(q, cands, specialize=True)
 
 
 def bench_channels(q, torch, amp_bytes):
@@ -379,7 +375,7 @@ def bench_density(args, torch, qs, synth):
             c[3] += 8 * (1 << (2 * k)) * (1 << (2 * n))   # 4^k x 4^k superoperator
         ab = 16 if prec == "c128" else 8
         out[prec] = {"value": logical / step_s, "ms_per_step": step_s * 1e3,
-                     "roofline": roofline(kinds, ab, 2 * n),
+                     "roofline": roofline(kinds, ab, "density14"),
                      "per_kind": per_kernel_table(kinds, ab),
                      "channels": bench_channels(q, torch, ab),
                      "special_ops": bench_special(q, torch, ab),
@@ -394,8 +390,7 @@ def bench_density(args, torch, qs, synth):
     q = qs.Qureg(n, density=True, precision="c64")
     circ = qs.Circuit(n, ops, density=True)
     cands = tuple(int(x) for x in args.fuse_candidates.split(","))
-    best_k, tune_ms = circ.autotune(q, cands)
-    spec = try_specialize(circ, q, best_k, torch, disabled=args.no_specialize)
+    best_k, tune_ms, spec_ms = autotune(circ, q, cands, args)
     q.init_zero()
     for _ in range(args.warmup):
         circ.apply(q)
@@ -414,7 +409,9 @@ def bench_density(args, torch, qs, synth):
     tr, pur = q.trace(), q.purity()
     st = circ.stats()
     fused = {"value": logical / step_s, "ms_per_step": step_s * 1e3, "fuse_k": best_k,
-             "autotune_ms": {str(k): v for k, v in tune_ms.items()}, "specialization": spec,
+             "autotune_ms": {str(k): v for k, v in tune_ms.items()},
+             "autotune_specialised_ms": spec_ms and {str(k): v for k, v in spec_ms.items()},
+             "specialised_kernels": circ.specialized,
              "passes": st["num_passes"], "max_amp_err_vs_c128": err, "per_kernel": per_kernel_table(kinds, 8),
              "partial_trace_ms": ta.elapsed_time(tb),
              "trace": [tr.real, tr.imag], "purity": [pur.real, pur.imag],
@@ -423,7 +420,7 @@ def bench_density(args, torch, qs, synth):
                      "c64 (f32)", "14-qubit density matrix (28-qubit Choi vector), 300 seeded ops: Haar 1/2-qubit "
                      "unitaries, depolarising, damping, random 2-qubit Kraus maps as superoperators; "
                      "partial trace over 7 qubits, trace, purity",
-                     {"roofline": roofline(kinds, 8, 2 * n), "fused_c64": fused,
+                     {"roofline": roofline(kinds, 8, "density14"), "fused_c64": fused,
                       "plain_c128": out["c128"], "plain_c64": out["c64"],
                       "speedup_fused_c64_vs_plain_c128": out["c128"]["ms_per_step"] / fused["ms_per_step"]})
     line["config"]["path"] = "complex64 density circuit, " + path_text(best_k, circ.specialized > 0)
@@ -482,7 +479,7 @@ def bench_sv34(args, torch, qs, synth):
         t = time_steps(circ, q, 1, torch)
         kinds = time_passes(circ, q, torch)
         res[label] = {"value": logical / t, "ms_per_step": t * 1e3, "passes": circ.stats()["num_passes"],
-                      "roofline": roofline(kinds, 8, n), "per_kernel": per_kernel_table(kinds, 8)}
+                      "roofline": roofline(kinds, 8, "sv34"), "per_kernel": per_kernel_table(kinds, 8)}
         del circ
     zz = np.zeros((1, n), np.int32)
     zz[0, 0] = zz[0, n - 1] = 3
@@ -518,6 +515,7 @@ def main():
     import paper_2311_01512_amd as qs
 
     n, seed = args.qubits, 11
+    workload = "circuit28" if (n, args.gates) == (28, 500) else f"circuit{n}_{args.gates}"
     ops = synth.config2_circuit(num_qubits=n, num_gates=args.gates)
     logical = synth.count_logical_updates(ops, n)
 
@@ -525,8 +523,7 @@ def main():
     q64 = qs.Qureg(n, precision="c64").init_hashed(seed)
     fused = qs.Circuit(n, ops)
     cands = tuple(int(x) for x in args.fuse_candidates.split(","))
-    best_k, tune_ms = fused.autotune(q64, cands)
-    spec = try_specialize(fused, q64, best_k, torch, disabled=args.no_specialize)
+    best_k, tune_ms, spec_ms = autotune(fused, q64, cands, args)
     # plain complex128, one pass per gate
     plain = qs.Circuit(n, ops).compile(0, "c128")
     q128 = qs.Qureg(n, precision="c128")
@@ -563,13 +560,15 @@ def main():
                                "2-target Haar with 0-3 controls, Pauli gadgets of weight 1-N)",
                    "num_qubits": n, "gates": len(ops),
                    "path": f"complex64, {path_text(best_k, fused.specialized > 0)} (fusion width autotuned)"},
-        "roofline": roofline(kinds64, 8, n),
+        "roofline": roofline(kinds64, 8, workload),
         "fused_c64": {"value": logical / t64, "ms_per_step": t64 * 1e3, "fuse_k": best_k,
-                      "autotune_ms": {str(k): v for k, v in tune_ms.items()}, "specialization": spec,
+                      "autotune_ms": {str(k): v for k, v in tune_ms.items()},
+                      "autotune_specialised_ms": spec_ms and {str(k): v for k, v in spec_ms.items()},
+                      "specialised_kernels": fused.specialized,
                       "passes": st["num_passes"], "passes_by_width": st["passes_by_width"],
                       "max_amp_err_vs_c128": err, "per_kernel": per_kernel_table(kinds64, 8)},
         "plain_c128": {"value": logical / t128, "ms_per_step": t128 * 1e3, "passes": len(ops),
-                       "roofline": roofline(kinds128, 16, n), "per_kernel": per_kernel_table(kinds128, 16)},
+                       "roofline": roofline(kinds128, 16, workload), "per_kernel": per_kernel_table(kinds128, 16)},
         "speedup_fused_c64_vs_plain_c128": t128 / t64,
         "special_ops_c128": bench_special(q128, torch, 16),
         "special_ops_c64": bench_special(q64, torch, 8),

@@ -372,6 +372,20 @@ int qs_circuit_pass_info(const qs_circuit *c, int index, int *kernel, int *num_t
  */
 int qs_circuit_autotune(qs_qureg *q, qs_circuit *c, const int *candidates, int num_candidates, int *best_k,
                         double *ms_out);
+/*
+ * The same, and with try_specialized != 0 each candidate that compiles into
+ * tile steps is timed a second time with its steps specialised
+ * (qs_circuit_specialize; candidates the run-time compiler cannot build are
+ * timed generic only).  The circuit is left compiled, and specialised if
+ * that was faster, as the fastest of all timings says: *best_k receives the
+ * width and *best_specialized (may be NULL) 1 for specialised steps.
+ * ms_specialized_out (may be NULL) receives num_candidates timings in ms, -1
+ * where no specialised form was timed.  Choices are cached as for
+ * qs_circuit_autotune, separately for try_specialized = 0 and != 0.
+ */
+int qs_circuit_autotune_ex(qs_qureg *q, qs_circuit *c, const int *candidates, int num_candidates,
+                           int try_specialized, int *best_k, int *best_specialized, double *ms_out,
+                           double *ms_specialized_out);
 
 /* ---- batches: many parametrised circuits of uneven size, with energies and
  *      adjoint gradients ------------------------------------------------------ */

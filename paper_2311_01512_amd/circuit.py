@@ -62,14 +62,25 @@ class Circuit:
     def pass_info(self, index):
         return N.qs_circuit_pass_info(self._c, index)
 
-    def autotune(self, qureg, candidates=(0, 3, 4, 5, 6)):
+    def autotune(self, qureg, candidates=(0, 3, 4, 5, 6), specialize=False):
         """Times one application per fusion width on `qureg` (overwriting its
         state) and leaves the circuit compiled with the fastest; returns
-        (best_k, {k: ms})."""
-        best, ms = N.qs_circuit_autotune(qureg.handle, self._c, candidates)
+        (best_k, {k: ms}).  With specialize=True, widths that give tile steps
+        are also timed with the steps specialised, the circuit is left in the
+        fastest form (`self.specialized` > 0 when that is specialised) and
+        the return value is (best_k, {k: ms}, {k: specialised ms})."""
+        if not specialize:
+            best, ms = N.qs_circuit_autotune(qureg.handle, self._c, candidates)
+            self.compiled_for = (best, qureg.precision)
+            self.specialized = 0
+            return best, dict(zip(candidates, ms.tolist()))
+        best, spec, ms, ms_spec = N.qs_circuit_autotune_ex(qureg.handle, self._c, candidates, True)
         self.compiled_for = (best, qureg.precision)
         self.specialized = 0
-        return best, dict(zip(candidates, ms.tolist()))
+        if spec:
+            self.specialized = sum(1 for i in range(self.stats()["num_passes"])
+                                   if self.pass_info(i)["kernel"] == "tile")
+        return best, dict(zip(candidates, ms.tolist())), {k: v for k, v in zip(candidates, ms_spec.tolist()) if v >= 0}
 
     def close(self):
         if getattr(self, "_c", None) is not None:

@@ -5,6 +5,13 @@
 
 #include "dev_core.hpp"
 
+// No implicit fusion of a multiply into an add for the rest of the
+// translation unit: the fused operations are the explicit fma calls, so the
+// generic kernel and a step compiled with its operators as constants round
+// alike (with contraction on, constants let the compiler fuse a different
+// product of the same expression).
+#pragma clang fp contract(off)
+
 namespace qs {
 
 // i-th lowest set bit of mask receives bit i of l

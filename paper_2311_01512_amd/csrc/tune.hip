@@ -57,7 +57,9 @@ int tile_low_qubits(int precision)
     return precision == QS_C64 ? 4 : 3;   // 128-byte runs
 }
 
-// (qubits, precision, circuit fingerprint) -> chosen fusion width
+// (qubits, precision (+4 when specialised steps were candidates), circuit
+// fingerprint) -> chosen fusion width, with kSpecialisedFlag set when the
+// tile steps run specialised
 using TuneKey = std::tuple<int, int, uint64_t>;
 static std::map<TuneKey, int> g_tuned;
 static std::mutex g_tune_mu;
@@ -92,45 +94,85 @@ static void append_cache_file(const TuneKey &key, int k)
 
 using namespace qs;
 
-extern "C" int qs_circuit_autotune(qs_qureg *q, qs_circuit *c, const int *candidates, int num_candidates,
-                                   int *best_k, double *ms_out)
+namespace {
+
+// A tuned choice: fusion width k, and whether the tile steps run as
+// specialised kernels (stored as k + kSpecialisedFlag).
+constexpr int kSpecialisedFlag = 1 << 16;
+
+// Applies the circuit once untimed (first touch, code loading) and once
+// between two events on q's stream; *ms receives the timed application.
+int time_application(qs_qureg *q, qs_circuit *c, hipEvent_t e0, hipEvent_t e1, float *ms)
+{
+    int rc = qs_apply_circuit(q, c);
+    if (rc != QS_OK) return rc;
+    if (hipEventRecord(e0, q->stream) != hipSuccess) return fail(QS_E_HIP, "hipEventRecord");
+    rc = qs_apply_circuit(q, c);
+    if (rc != QS_OK) return rc;
+    if (hipEventRecord(e1, q->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return fail(QS_E_HIP, "event timing failed");
+    *ms = 0.f;
+    (void)hipEventElapsedTime(ms, e0, e1);
+    return QS_OK;
+}
+
+// Leaves the circuit compiled (and specialised) as `choice` says.
+int apply_choice(qs_circuit *c, int choice, int precision)
+{
+    int rc = qs_circuit_compile(c, choice & (kSpecialisedFlag - 1), precision);
+    if (rc == QS_OK && (choice & kSpecialisedFlag)) rc = qs_circuit_specialize(c, nullptr);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int qs_circuit_autotune_ex(qs_qureg *q, qs_circuit *c, const int *candidates, int num_candidates,
+                                      int try_specialized, int *best_k, int *best_specialized, double *ms_out,
+                                      double *ms_specialized_out)
 {
     if (!q || !c || !candidates || num_candidates < 1) return fail(QS_E_ARG, "bad autotune arguments");
     if (q->num_qubits != circuit_num_qubits(c)) return fail(QS_E_ARG, "qubit counts differ");
-    const TuneKey key(q->num_qubits, q->precision, circuit_fingerprint(c));
+    const TuneKey key(q->num_qubits, q->precision + (try_specialized ? 4 : 0), circuit_fingerprint(c));
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_cache_file();
         auto it = g_tuned.find(key);
-        if (it != g_tuned.end() && !ms_out) {
-            if (best_k) *best_k = it->second;
-            return qs_circuit_compile(c, it->second, q->precision);
+        if (it != g_tuned.end() && !ms_out && !ms_specialized_out) {
+            if (best_k) *best_k = it->second & (kSpecialisedFlag - 1);
+            if (best_specialized) *best_specialized = (it->second & kSpecialisedFlag) != 0;
+            return apply_choice(c, it->second, q->precision);
         }
     }
     hipEvent_t e0, e1;
     QS_HIP(hipEventCreate(&e0));
-    QS_HIP(hipEventCreate(&e1));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(QS_E_HIP, "hipEventCreate");
+    }
     int best = candidates[0];
     float best_ms = 1e30f;
     int rc = QS_OK;
     for (int i = 0; i < num_candidates && rc == QS_OK; i++) {
+        if (ms_specialized_out) ms_specialized_out[i] = -1.0;
         rc = qs_circuit_compile(c, candidates[i], q->precision);
         if (rc != QS_OK) break;
-        rc = qs_apply_circuit(q, c);   // untimed: first-touch and code loading
-        if (rc != QS_OK) break;
-        if (hipEventRecord(e0, q->stream) != hipSuccess) { rc = fail(QS_E_HIP, "hipEventRecord"); break; }
-        rc = qs_apply_circuit(q, c);
-        if (rc != QS_OK) break;
-        if (hipEventRecord(e1, q->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-            rc = fail(QS_E_HIP, "event timing failed");
-            break;
-        }
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
+        rc = time_application(q, c, e0, e1, &ms);
+        if (rc != QS_OK) break;
         if (ms_out) ms_out[i] = ms;
         if (ms < best_ms) {
             best_ms = ms;
             best = candidates[i];
+        }
+        if (!try_specialized) continue;
+        int kernels = 0;
+        if (qs_circuit_specialize(c, &kernels) != QS_OK || kernels == 0) continue;   // no tile steps, or no compiler
+        rc = time_application(q, c, e0, e1, &ms);
+        if (rc != QS_OK) break;
+        if (ms_specialized_out) ms_specialized_out[i] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = candidates[i] | kSpecialisedFlag;
         }
     }
     (void)hipEventDestroy(e0);
@@ -141,6 +183,13 @@ extern "C" int qs_circuit_autotune(qs_qureg *q, qs_circuit *c, const int *candid
         g_tuned[key] = best;
         append_cache_file(key, best);
     }
-    if (best_k) *best_k = best;
-    return qs_circuit_compile(c, best, q->precision);
+    if (best_k) *best_k = best & (kSpecialisedFlag - 1);
+    if (best_specialized) *best_specialized = (best & kSpecialisedFlag) != 0;
+    return apply_choice(c, best, q->precision);
+}
+
+extern "C" int qs_circuit_autotune(qs_qureg *q, qs_circuit *c, const int *candidates, int num_candidates,
+                                   int *best_k, double *ms_out)
+{
+    return qs_circuit_autotune_ex(q, c, candidates, num_candidates, 0, best_k, nullptr, ms_out, nullptr);
 }

@@ -87,6 +87,7 @@ _SIGS = {
     "qs_circuit_pass_info": [_P, _I, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                              C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "qs_circuit_autotune": [_P, _P, _P, _I, C.POINTER(C.c_int), _PD],
+    "qs_circuit_autotune_ex": [_P, _P, _P, _I, _I, C.POINTER(C.c_int), C.POINTER(C.c_int), _PD, _PD],
     "qs_batch_create": [_I, _PP],
     "qs_batch_destroy": [_P],
     "qs_batch_add_circuit": [_P, _I, _I, C.POINTER(C.c_int)],
@@ -405,6 +406,17 @@ def qs_circuit_autotune(q, c, candidates):
     check(lib.qs_circuit_autotune(q, c, ptr(cand), cand.size, C.byref(best),
                                   ms.ctypes.data_as(_PD)), "qs_circuit_autotune")
     return best.value, ms
+
+
+def qs_circuit_autotune_ex(q, c, candidates, try_specialized):
+    cand = ints(candidates)
+    best, spec = C.c_int(), C.c_int()
+    ms = np.zeros(cand.size, dtype=np.float64)
+    ms_spec = np.zeros(cand.size, dtype=np.float64)
+    check(lib.qs_circuit_autotune_ex(q, c, ptr(cand), cand.size, int(bool(try_specialized)), C.byref(best),
+                                     C.byref(spec), ms.ctypes.data_as(_PD), ms_spec.ctypes.data_as(_PD)),
+          "qs_circuit_autotune_ex")
+    return best.value, bool(spec.value), ms, ms_spec
 
 
 # ---- batches -------------------------------------------------------------------

@@ -125,3 +125,49 @@ def test_disk_cache(qs, tmp_path, monkeypatch):
     q.set_amps(psi)
     c2.apply(q)
     assert np.array_equal(q.get_amps(), generic)
+
+
+def test_whole_circuit_equals_generic(qs):
+    """Two applications of a 24-qubit circuit: the specialised steps round
+    exactly as the generic kernel does (no implicit contraction of products
+    into sums in either build)."""
+    banner("whole circuit, specialised vs generic")
+    import torch
+    N = 24
+    ops = synth.config2_circuit(num_qubits=N, num_gates=500)
+    cg = qs.Circuit(N, ops).compile(12, "c64")
+    cs = qs.Circuit(N, ops).compile(12, "c64")
+    cs.specialize()
+    qg = qs.Qureg(N, precision="c64").init_hashed(7)
+    qx = qs.Qureg(N, precision="c64").init_hashed(7)
+    for _ in range(2):
+        cg.apply(qg)
+        cs.apply(qx)
+    qg.sync()
+    qx.sync()
+    assert torch.equal(qg.tensor, qx.tensor)
+
+
+def test_autotune_with_specialised_steps(qs):
+    """The autotuner times tile widths generic and specialised and leaves the
+    circuit in the fastest form; the result still matches the oracle."""
+    banner("autotune with specialised steps")
+    N = 14
+    ops = synth.config2_circuit(num_qubits=N, num_gates=120, seed=75)
+    rng = np.random.default_rng(75)
+    psi = synth.random_state(rng, 1 << N)
+    c = qs.Circuit(N, ops)
+    q = qs.Qureg(N, precision="c64").init_zero()
+    best, ms, ms_spec = c.autotune(q, (0, 4, 11, 12), specialize=True)
+    assert best in (0, 4, 11, 12)
+    assert set(ms) == {0, 4, 11, 12}
+    assert set(ms_spec) == {11, 12}                  # only tile widths have a specialised form
+    assert all(v > 0 for v in ms_spec.values())
+    fastest = min(min(ms.values()), min(ms_spec.values()))
+    chosen = ms_spec[best] if c.specialized else ms[best]
+    assert chosen == fastest
+    q.set_amps(psi)
+    c.apply(q)
+    assert amp_err(q.get_amps(), oracle.run_ops(psi.copy(), ops)) < TOL["c64"]
+    best2, _ = c.autotune(q, (0, 4))                 # the plain autotuner: no specialised steps
+    assert c.specialized == 0 and best2 in (0, 4)
