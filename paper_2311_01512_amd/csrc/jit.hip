@@ -23,6 +23,7 @@
 #include <cinttypes>
 #include <cstdio>
 #include <cstdlib>
+#include <complex>
 #include <cstring>
 #include <fstream>
 #include <functional>
@@ -101,16 +102,49 @@ std::string op_init(const ROp &r)
     return o.str();
 }
 
+// Register bits of a dense (codes 1-7, 17-23) or sparse (64+) register
+// operator, 0 for other codes.
+int matrix_bits(int c)
+{
+    if (c >= 1 && c <= 7) return c;
+    if (c >= 17 && c <= 23) return c - 16;
+    if (c >= 64) return (c - 64) >> 2;
+    return 0;
+}
+
+// The matrix of a dense or sparse register operator as a constexpr array
+// `M` holding the values of the pass's device table (FP32 for complex64).
+std::string matrix_init(const Pass &p, const ROp &r, bool f32)
+{
+    const int bits = matrix_bits(r.code);
+    const int n = 1 << (2 * __builtin_popcount((unsigned)bits));
+    std::ostringstream o;
+    o << "static constexpr " << (f32 ? "float2" : "double2") << " M[" << n << "] = {";
+    for (int i = 0; i < n; i++) {
+        const std::complex<double> &v = p.tmats[(size_t)r.mat + i];
+        o << (i ? ", " : "") << (f32 ? "float2{" : "double2{");
+        if (f32)
+            o << hexf((float)v.real()) << ", " << hexf((float)v.imag());
+        else
+            o << hexd(v.real()) << ", " << hexd(v.imag());
+        o << "}";
+    }
+    o << "};";
+    return o.str();
+}
+
 // The call that applies operator `name` (a constexpr ROp) in a phase; empty
-// for codes the generic kernel ignores as well.
+// for codes the generic kernel ignores as well.  Dense and sparse register
+// operators take their matrix from the constexpr array M (the entries end up
+// as instruction literals instead of loads into scalar registers).
 std::string op_call(const ROp &r, const std::string &name, bool f32)
 {
     const int c = r.code;
     std::ostringstream o;
     if (c >= 1 && c <= 7)
-        o << "qs::reg_dense<R, " << c << ", false>(x, " << name << ", tau, base, mats + " << r.mat << ");";
+        o << "qs::reg_dense<R, " << c << ", false>(x, " << name << ", tau, base, M);";
     else if (c >= 17 && c <= 23)
-        o << "qs::reg_dense<R, " << c - 16 << ", true>(x, " << name << ", tau, base, mats + " << r.mat << ");";
+        o << "qs::reg_dense<R, " << c - 16 << ", true>(x, " << name << ", tau, base, M);";
     else if (c >= 8 && c <= 15)
         o << "qs::reg_gadget<R, " << c - 8 << ">(x, " << name << ", tau, base);";
     else if (c == 16)
@@ -123,7 +157,7 @@ std::string op_call(const ROp &r, const std::string &name, bool f32)
         o << "qs::mfma_dense<" << c - 32 << ">(x, " << name << ", tau, base, mats);";
     else if (c >= 64) {
         const int um = (c - 64) >> 2, sm = (c - 64) & 3;
-        o << "qs::reg_sparse<R, " << um << ", " << sm << ">(x, mats + " << r.mat << ");";
+        o << "qs::reg_sparse<R, " << um << ", " << sm << ">(x, M);";
     }
     return o.str();
 }
@@ -160,7 +194,9 @@ std::string step_kernel(const Pass &p, int index, bool f32)
         for (int oi = P.first_op; oi < P.first_op + P.num_ops; oi++) {
             const std::string call = op_call(p.rops[oi], "O", f32);
             if (call.empty()) continue;
-            o << "        { constexpr qs::ROp O = " << op_init(p.rops[oi]) << "; " << call << " }\n";
+            o << "        { constexpr qs::ROp O = " << op_init(p.rops[oi]) << "; ";
+            if (matrix_bits(p.rops[oi].code)) o << matrix_init(p, p.rops[oi], f32) << " ";
+            o << call << " }\n";
         }
     }
     o << "    });\n}\n\n";
