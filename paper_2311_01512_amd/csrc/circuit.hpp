@@ -47,6 +47,7 @@ struct Pass {
     // kernel specialised for this step at run time (jit.hip), or null
     void *jit_fn = nullptr;
     unsigned jit_grid = 0;            // its resident-block grid
+    unsigned jit_lds = 0;             // its dynamic LDS bytes (tile, then staged tables)
 };
 
 // LDS tile engine (tiles.hip).

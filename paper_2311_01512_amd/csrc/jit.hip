@@ -162,8 +162,70 @@ std::string op_call(const ROp &r, const std::string &name, bool f32)
     return o.str();
 }
 
+// Matrix-core operators of a specialised step read their per-lane
+// coefficients from LDS: the variants their register groups use are copied
+// once per block, behind the tile.  (Read from global memory for every tile,
+// as the generic kernel does, these loads missed L2 nearly every time.)
+// Offsets and lengths in floats; `ops` maps an operator's index to its
+// (mat, hsel) relative to the LDS tables.
+struct MfmaStage {
+    std::vector<unsigned> src, dst, len, width, lane_floats;   // width: chunk TW; lane_floats: NB * KS
+    std::map<int, std::pair<int, uint32_t>> ops;
+    unsigned floats = 0;
+};
+
+MfmaStage stage_mfma(const Pass &p)
+{
+    MfmaStage st;
+    for (size_t oi = 0; oi < p.rops.size(); oi++) {
+        const ROp &r = p.rops[oi];
+        if (r.code < 32 || r.code > 38) continue;
+        const int rm = r.code - 32;
+        const int regs = 1 << __builtin_popcount((unsigned)rm);
+        const unsigned lane_floats = (unsigned)(regs >= 2 ? regs / 2 : 1) * (unsigned)(2 * regs);
+        const unsigned per_variant = 64u * lane_floats;
+        int slot_of[4] = {-1, -1, -1, -1}, slots = 0;
+        uint32_t hsel = 0;
+        const unsigned first = st.floats;
+        for (int u0 = 0; u0 < kRegs; u0++) {
+            if (u0 & rm) continue;
+            const int h = (int)((r.hsel >> (2 * u0)) & 3u);
+            if (slot_of[h] < 0) {
+                slot_of[h] = slots++;
+                st.src.push_back(2u * (unsigned)r.mat + (unsigned)h * per_variant);
+                st.dst.push_back(st.floats);
+                st.len.push_back(per_variant);
+                st.width.push_back(std::min(4u, lane_floats));
+                st.lane_floats.push_back(lane_floats);
+                st.floats += per_variant;
+            }
+            hsel |= (uint32_t)slot_of[h] << (2 * u0);
+        }
+        st.ops[(int)oi] = {(int)(first / 2), hsel};
+    }
+    return st;
+}
+
+// The staging of a step, empty when there is nothing to stage or the tile
+// and the tables would not fit the LDS a block may have (max_lds): such a
+// step reads the coefficients from global memory.
+MfmaStage stage_for(const Pass &p, bool f32, size_t max_lds)
+{
+    if (!f32) return MfmaStage{};
+    MfmaStage st = stage_mfma(p);
+    if (((size_t)1 << p.tile_d) * sizeof(float2) + 4 * (size_t)st.floats > max_lds) return MfmaStage{};
+    return st;
+}
+
+// Bytes of LDS a specialised step needs: the tile, then the staged tables.
+size_t step_lds_bytes(const Pass &p, bool f32, size_t max_lds)
+{
+    return ((size_t)1 << p.tile_d) * (f32 ? sizeof(float2) : sizeof(double2)) +
+           4 * (size_t)stage_for(p, f32, max_lds).floats;
+}
+
 // One kernel per tile pass, named qs_step_<index>.
-std::string step_kernel(const Pass &p, int index, bool f32)
+std::string step_kernel(const Pass &p, int index, bool f32, size_t max_lds)
 {
     const int lb = p.tile_d - kRegBits;
     const int block = 1 << lb;
@@ -185,6 +247,34 @@ std::string step_kernel(const Pass &p, int index, bool f32)
     o << "}};\n";
     for (size_t k = 0; k < p.phases.size(); k++)
         o << "    constexpr qs::RPhase P" << k << " = " << phase_init(p.phases[k]) << ";\n";
+    const MfmaStage st = stage_for(p, f32, max_lds);
+    const size_t tile_bytes = ((size_t)1 << p.tile_d) * (f32 ? sizeof(float2) : sizeof(double2));
+    if (!st.src.empty()) {
+        auto ulist = [](const std::vector<unsigned> &v) {
+            std::string t = "{";
+            for (size_t i = 0; i < v.size(); i++) t += (i ? ", " : "") + std::to_string(v[i] / 2) + "u";
+            return t + "}";
+        };
+        // float2 units
+        o << "    const float2 *tabs = reinterpret_cast<const float2 *>(lds_raw + " << tile_bytes << ");\n";
+        auto plain = [](const std::vector<unsigned> &v) {
+            std::string t = "{";
+            for (size_t i = 0; i < v.size(); i++) t += (i ? ", " : "") + std::to_string(v[i]) + "u";
+            return t + "}";
+        };
+        // chunk c: float2 e of the LDS copy is floats d = 2e, 2e + 1 of lane
+        // (d / W) % 64, chunk (d / W) / 64, from the lane's floats in memory
+        o << "    {\n        constexpr unsigned cs[] = " << ulist(st.src) << ", cd[] = " << ulist(st.dst)
+          << ", cl[] = " << ulist(st.len) << ", cw[] = " << plain(st.width) << ", cn[] = " << plain(st.lane_floats)
+          << ";\n";
+        o << "        float2 *dst = reinterpret_cast<float2 *>(lds_raw + " << tile_bytes << ");\n";
+        o << "#pragma unroll\n        for (int c = 0; c < " << st.src.size() << "; c++)\n";
+        o << "            for (unsigned e = threadIdx.x; e < cl[c]; e += " << block << "u) {\n";
+        o << "                const unsigned d = 2u * e, v = d / cw[c];\n";
+        o << "                dst[cd[c] + e] = mats[cs[c] + ((v & 63u) * cn[c] + (v >> 6) * cw[c] + d % cw[c]) / 2u];\n";
+        o << "            }\n";
+        o << "        __syncthreads();\n    }\n";
+    }
     o << "    qs::tile_walk<R>(a, num_tiles, plan, P0, P" << p.phases.size() - 1 << ", " << lb
       << ", [&](qs::C2<R> (&x)[qs::kRegs], uint64_t base) {\n";
     o << "        uint32_t tau = qs::tau_of(threadIdx.x, P0);\n";
@@ -192,9 +282,20 @@ std::string step_kernel(const Pass &p, int index, bool f32)
         const RPhase &P = p.phases[k];
         if (k > 0) o << "        tau = qs::tile_exchange<R>(x, lds_raw, tau, P" << k - 1 << ", P" << k << ");\n";
         for (int oi = P.first_op; oi < P.first_op + P.num_ops; oi++) {
-            const std::string call = op_call(p.rops[oi], "O", f32);
+            ROp r = p.rops[oi];
+            std::string call = op_call(r, "O", f32);
             if (call.empty()) continue;
-            o << "        { constexpr qs::ROp O = " << op_init(p.rops[oi]) << "; ";
+            auto it = st.ops.find(oi);
+            if (it != st.ops.end()) {
+                // coefficients from the LDS tables
+                r.mat = it->second.first;
+                r.hsel = it->second.second;
+                const int rm = r.code - 32, regs = 1 << __builtin_popcount((unsigned)rm);
+                const int lane_floats = (regs >= 2 ? regs / 2 : 1) * 2 * regs;
+                call = "qs::mfma_dense<" + std::to_string(rm) + ", " + std::to_string(std::min(4, lane_floats)) +
+                       ">(x, O, tau, base, tabs);";
+            }
+            o << "        { constexpr qs::ROp O = " << op_init(r) << "; ";
             if (matrix_bits(p.rops[oi].code)) o << matrix_init(p, p.rops[oi], f32) << " ";
             o << call << " }\n";
         }
@@ -379,7 +480,7 @@ int compile(const std::vector<std::string> &srcs, const std::string &arch, std::
 
 // Sources of the tile passes of a compiled circuit (kernel name = pass
 // index), split into `chunks` files of about equal kernel counts.
-std::vector<std::string> specialized_sources(const qs_circuit *c, int chunks)
+std::vector<std::string> specialized_sources(const qs_circuit *c, int chunks, size_t max_lds)
 {
     const bool f32 = c->precision == QS_C64;
     std::vector<int> idx;
@@ -387,7 +488,7 @@ std::vector<std::string> specialized_sources(const qs_circuit *c, int chunks)
         if (c->passes[i].tile && !c->passes[i].phases.empty()) idx.push_back((int)i);
     chunks = std::max(1, std::min<int>(chunks, (int)idx.size()));
     std::vector<std::string> out(chunks, "#include \"tile_dev.hpp\"\n\n");
-    for (size_t j = 0; j < idx.size(); j++) out[j * chunks / idx.size()] += step_kernel(c->passes[idx[j]], idx[j], f32);
+    for (size_t j = 0; j < idx.size(); j++) out[j * chunks / idx.size()] += step_kernel(c->passes[idx[j]], idx[j], f32, max_lds);
     return out;
 }
 
@@ -396,6 +497,7 @@ void release_specialized(qs_circuit *c)
     for (auto &p : c->passes) {
         p.jit_fn = nullptr;
         p.jit_grid = 0;
+        p.jit_lds = 0;
     }
     for (void *m : c->jit_modules) (void)hipModuleUnload((hipModule_t)m);
     c->jit_modules.clear();
@@ -420,7 +522,8 @@ int specialize_tiles(qs_circuit *c, int *num_kernels)
     // several compilers at once: a few kernels per child process
     const int chunks = std::max(1, std::min(8, (count + 3) / 4));
     std::vector<std::vector<char>> codes;
-    int rc = compile(specialized_sources(c, chunks), arch, codes);
+    const size_t max_lds = prop.sharedMemPerBlock;
+    int rc = compile(specialized_sources(c, chunks, max_lds), arch, codes);
     if (rc != QS_OK) return rc;
     for (const auto &code : codes) {
         hipModule_t mod;
@@ -433,7 +536,6 @@ int specialize_tiles(qs_circuit *c, int *num_kernels)
     }
     int cus = 0;
     QS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const size_t ab = c->precision == QS_C64 ? sizeof(float2) : sizeof(double2);
     int j = 0;
     for (size_t i = 0; i < c->passes.size(); i++) {
         Pass &p = c->passes[i];
@@ -449,13 +551,14 @@ int specialize_tiles(qs_circuit *c, int *num_kernels)
         }
         int per_cu = 0;
         const int block = 1 << (p.tile_d - kRegBits);
-        const size_t lds = ((size_t)1 << p.tile_d) * ab;
+        const size_t lds = step_lds_bytes(p, c->precision == QS_C64, max_lds);
         if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, block, lds) != hipSuccess || per_cu < 1) {
             release_specialized(c);
             return fail(QS_E_HIP, "occupancy query for " + name + " failed");
         }
         p.jit_fn = (void *)f;
         p.jit_grid = (unsigned)(per_cu * cus);
+        p.jit_lds = (unsigned)lds;
     }
     return QS_OK;
 }

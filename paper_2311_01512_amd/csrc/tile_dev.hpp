@@ -219,13 +219,18 @@ __device__ __forceinline__ void reg_scale(C2<R> (&x)[kRegs], const ROp &op)
 // register group one v_mfma_f32_16x16x4f32 K-step takes the real or the
 // imaginary parts of one register; the output lands in the lane that holds
 // the member (coefficients from mfma_coeffs).
-template <int RM>
+//
+// Coefficient layout: TW = 0, as the host writes them (each lane's NB * KS
+// floats contiguous); TW > 0, the copy staged in LDS, in chunks of TW floats
+// with the 64 lanes' chunks side by side, so that a wavefront reads 64
+// consecutive chunks at once (no bank conflicts).
+template <int RM, int TW = 0>
 __device__ __forceinline__ void mfma_dense(float2 (&x)[kRegs], const ROp &op, uint32_t tau, uint64_t base,
                                            const float2 *__restrict__ mats)
 {
     typedef float f32x4 __attribute__((ext_vector_type(4)));
     constexpr int R = 1 << popcount_c(RM), KS = 2 * R, NB = R >= 2 ? R / 2 : 1;
-    const float *A0 = reinterpret_cast<const float *>(mats + op.mat) + (threadIdx.x & 63u) * (NB * KS);
+    const float *A0 = reinterpret_cast<const float *>(mats + op.mat) + (threadIdx.x & 63u) * (TW ? TW : NB * KS);
     uint32_t tp = 0;
     for (int i = 0; i < op.nc; i++)
         tp |= (uint32_t)(((base >> op.cq[i]) ^ (uint64_t)__popc(tau & op.cm[i])) & 1ULL) << i;
@@ -249,7 +254,20 @@ __device__ __forceinline__ void mfma_dense(float2 (&x)[kRegs], const ROp &op, ui
         for (int blk = 0; blk < NB; blk++) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s = 0; s < KS; s++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[blk * KS + s], b[s], acc, 0, 0, 0);
+            for (int s = 0; s < KS; s++) {
+                const int f = blk * KS + s;
+                float a;
+                if constexpr (TW == 4) {
+                    // one 16-byte read per chunk (the LDS copy is 16-byte aligned)
+                    const f32x4 v = *reinterpret_cast<const f32x4 *>(A + (f / 4) * 256);
+                    a = v[f % 4];
+                } else if constexpr (TW != 0) {
+                    a = A[(f / (TW ? TW : 1)) * 64 * TW + f % (TW ? TW : 1)];
+                } else {
+                    a = A[f];
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[s], acc, 0, 0, 0);
+            }
 #pragma unroll
             for (int i = 0; i < 4; i += 2) {
                 const int r = (4 * blk + i) / 2;

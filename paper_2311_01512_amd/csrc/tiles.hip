@@ -655,7 +655,7 @@ int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev)
         const void *mp = mats;
         void *args[] = {&a, &nt, &mp};
         const unsigned grid = grid_for(nt, 1, p.jit_grid);
-        QS_HIP(hipModuleLaunchKernel((hipFunction_t)p.jit_fn, grid, 1, 1, block, 1, 1, (unsigned)lds, q->stream, args,
+        QS_HIP(hipModuleLaunchKernel((hipFunction_t)p.jit_fn, grid, 1, 1, block, 1, 1, p.jit_lds, q->stream, args,
                                      nullptr));
         return QS_OK;
     }

@@ -66,6 +66,32 @@ def test_every_specialized_pass_equals_generic(qs, N, k, prec, seed):
     assert bad == []
 
 
+@pytest.mark.parametrize("k", [11, 12])
+def test_every_specialized_density_pass_equals_generic(qs, k):
+    """Density steps with matrix-core superoperators, whose coefficients the
+    specialised kernels stage in LDS: each step bit for bit against the
+    generic kernel on an 11-qubit density matrix (22 index bits)."""
+    banner(f"every specialised density pass k={k}")
+    import torch
+    N = 11
+    ops, _ = synth.config3_circuit(num_qubits=N, num_ops=200, seed=76)
+    cg = qs.Circuit(N, ops, density=True).compile(k, "c64")
+    cs = qs.Circuit(N, ops, density=True).compile(k, "c64")
+    assert cs.specialize() > 0
+    qg = qs.Qureg(N, density=True, precision="c64").init_hashed(7)
+    qx = qs.Qureg(N, density=True, precision="c64")
+    bad = []
+    for i in range(cg.stats()["num_passes"]):
+        qx.tensor.copy_(qg.tensor)
+        cg.apply_passes(qg, i, 1)
+        cs.apply_passes(qx, i, 1)
+        qx.sync()
+        qg.sync()
+        if not torch.equal(qg.tensor, qx.tensor):
+            bad.append(i)
+    assert bad == []
+
+
 def test_specialized_density_circuit(qs):
     """A density circuit with Kraus maps as sparse and matrix-core operators."""
     banner("specialised density circuit")
