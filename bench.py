@@ -465,7 +465,7 @@ def bench_sv34(args, torch, qs, synth):
     """34-qubit complex64 statevector (2^34 amplitudes, 128 GiB): 200 gates of
     5-target Haar unitaries with up to 4 controls and Pauli gadgets of weight
     up to 34, plain per-gate vs dense blocks (k = 6) vs tile steps of 2^12
-    amplitudes (5-target gates stay single passes there), one application
+    amplitudes, specialised (5-target gates stay single passes there), one application
     each (the faster fused path is the headline); <Z_0 Z_33> and norm in FP64."""
     import numpy as np
     n = 34
@@ -476,9 +476,12 @@ def bench_sv34(args, torch, qs, synth):
     norm0 = q.total_prob()
     for label, k in (("plain_c64", 0), ("fused_c64", 6), ("tiled_c64", 12)):
         circ = qs.Circuit(n, ops).compile(k, "c64")
+        if k >= 8 and not args.no_specialize:
+            circ.specialize()          # tile steps as kernels of their own (one 5 s application per timing)
         t = time_steps(circ, q, 1, torch)
         kinds = time_passes(circ, q, torch)
         res[label] = {"value": logical / t, "ms_per_step": t * 1e3, "passes": circ.stats()["num_passes"],
+                      "specialised_kernels": circ.specialized,
                       "roofline": roofline(kinds, 8, "sv34"), "per_kernel": per_kernel_table(kinds, 8)}
         del circ
     zz = np.zeros((1, n), np.int32)

@@ -26,6 +26,45 @@ struct CircOp {
     }
 };
 
+// Qubit masks of a recorded operator for commutation tests: a gadget as its
+// Pauli string X^x Z^z (Y sets both), a unitary as its targets and controls.
+struct OpMasks {
+    bool gadget = false;
+    uint64_t x = 0, z = 0, t = 0, c = 0;
+};
+
+inline OpMasks op_masks(const CircOp &op)
+{
+    OpMasks m;
+    m.gadget = op.gadget;
+    if (op.gadget) {
+        for (size_t k = 0; k < op.targs.size(); k++) {
+            const uint64_t b = 1ULL << op.targs[k];
+            if (op.paulis[k] == 1 || op.paulis[k] == 2) m.x |= b;
+            if (op.paulis[k] == 2 || op.paulis[k] == 3) m.z |= b;
+        }
+    } else {
+        for (int q : op.targs) m.t |= 1ULL << q;
+        for (int q : op.ctrls) m.c |= 1ULL << q;
+    }
+    return m;
+}
+
+// Whether the two operators commute (a sufficient test): Pauli gadgets when
+// their strings commute (an even number of qubits where they anticommute);
+// a gadget and a gate when the gadget is the identity on the gate's targets
+// and the identity or Z on its controls; two gates when no target of either
+// is a qubit of the other (shared controls commute).
+inline bool ops_commute(const OpMasks &a, const OpMasks &b)
+{
+    if (a.gadget && b.gadget) return (__builtin_popcountll((a.x & b.z) ^ (a.z & b.x)) & 1) == 0;
+    if (a.gadget || b.gadget) {
+        const OpMasks &g = a.gadget ? a : b, &u = a.gadget ? b : a;
+        return ((g.x | g.z) & u.t) == 0 && (g.x & u.c) == 0;
+    }
+    return (a.t & (b.t | b.c)) == 0 && (b.t & a.c) == 0;
+}
+
 struct Pass {
     bool gadget;
     std::vector<int> ctrls, sorted_targs;

@@ -81,13 +81,6 @@ static std::vector<uint64_t> needed_vectors(const CircOp &op)
     return v;
 }
 
-static uint64_t support_mask(const CircOp &op)
-{
-    uint64_t s = 0;
-    for (int q : op.support()) s |= 1ULL << q;
-    return s;
-}
-
 int tile_dim_limit(int precision)
 {
     int dev = 0, max_lds = 65536;
@@ -320,24 +313,29 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
     // pass 2^64.
     double scale = 1.0, growth = 1.0;
     std::vector<std::pair<size_t, size_t>> mat_range;   // tmats entries of each operator
-    // A phase takes, in order, every remaining member that fits it and shares
-    // no qubit with a remaining member it jumps over.
+    // A phase takes, in order, every remaining member that fits it and
+    // commutes with each remaining member it jumps over.
     std::vector<size_t> remaining(members.size());
     for (size_t m = 0; m < members.size(); m++) remaining[m] = m;
+    std::vector<OpMasks> mmask(members.size());
+    for (size_t m = 0; m < members.size(); m++) mmask[m] = op_masks(*members[m]);
     while (!remaining.empty()) {
         PhaseBuild B;
         std::vector<size_t> chosen, rest;
         std::vector<int> mode;
-        uint64_t blocked = 0;
         for (size_t m : remaining) {
-            const uint64_t s = support_mask(*members[m]);
+            bool free = true;
+            for (size_t k : rest)
+                if (!ops_commute(mmask[m], mmask[k])) {
+                    free = false;
+                    break;
+                }
             int md = -1;
-            if (!(s & blocked)) md = try_fit(B, m);
+            if (free) md = try_fit(B, m);
             if (md >= 0) {
                 chosen.push_back(m);
                 mode.push_back(md);
             } else {
-                blocked |= s;
                 rest.push_back(m);
             }
         }
@@ -532,6 +530,8 @@ void plan_tiles(qs_circuit *c, int T, int precision)
     const bool mfma = precision == QS_C64 && T >= kRegBits + 6;
     const int lookahead = 512;
     std::vector<char> placed(n_ops, 0);
+    std::vector<OpMasks> masks(n_ops);
+    for (int i = 0; i < n_ops; i++) masks[i] = op_masks(c->ops[i]);
     for (int i = 0; i < n_ops; i++) {
         if (placed[i]) continue;
         const CircOp &first = c->ops[i];
@@ -546,13 +546,20 @@ void plan_tiles(qs_circuit *c, int T, int precision)
         Echelon E;
         for (int b = 0; b < C; b++) E.add(1ULL << b);
         std::vector<const CircOp *> members;
-        uint64_t blocked = 0;
+        // operators the step leaves out: a later operator joins only if it
+        // commutes with every one of them
+        std::vector<int> skipped;
         for (int j = i; j < n_ops && j < i + lookahead; j++) {
             if (placed[j]) continue;
             const CircOp &op = c->ops[j];
-            const uint64_t s = support_mask(op);
-            if (s & blocked) {
-                blocked |= s;
+            bool free = true;
+            for (int k : skipped)
+                if (!ops_commute(masks[j], masks[k])) {
+                    free = false;
+                    break;
+                }
+            if (!free) {
+                skipped.push_back(j);
                 continue;
             }
             const std::vector<uint64_t> need = needed_vectors(op);
@@ -561,9 +568,8 @@ void plan_tiles(qs_circuit *c, int T, int precision)
                 members.push_back(&op);
                 placed[j] = 1;
             } else {
-                blocked |= s;
+                skipped.push_back(j);
             }
-            if (__builtin_popcountll(blocked) >= N) break;
         }
         // fill the tile to T dimensions with the lowest free qubits: longer
         // contiguous runs, fewer and larger tiles

@@ -253,3 +253,49 @@ def test_random_circuits_every_compile(qs, seed):
             q = qs.Qureg(N, precision=prec).set_amps(psi)
             circ.apply(q)
             assert amp_err(q.get_amps(), want) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("k", [8, 9, 10])
+def test_tiles_move_commuting_operators(qs, k, prec):
+    """Tile steps move an operator ahead of skipped ones it commutes with:
+    gadgets whose Pauli strings commute though they overlap (XX and ZZ on the
+    same pair, Z strings), gadgets that are Z on a gate's controls, gates that
+    share only controls; mixed with pairs that do not commute."""
+    banner(f"commuting operators k={k} {prec}")
+    rng = np.random.default_rng(31 + k)
+    N = 12
+    ops = []
+    for g in range(160):
+        a, b, c, d = (int(x) for x in rng.permutation(N)[:4])
+        kind = g % 6
+        if kind == 0:
+            ops.append({"op": "gadget", "targs": (a, b), "paulis": (1, 1), "theta": rng.uniform(-3, 3)})
+            ops.append({"op": "gadget", "targs": (a, b), "paulis": (3, 3), "theta": rng.uniform(-3, 3)})
+        elif kind == 1:
+            ops.append({"op": "unitary", "ctrls": (c,), "targs": (a, b), "matrix": synth.haar_unitary(rng, 4)})
+            ops.append({"op": "gadget", "targs": (c, d), "paulis": (3, 3),
+                        "theta": rng.uniform(-3, 3)})
+        elif kind == 2:
+            ops.append({"op": "unitary", "ctrls": (c,), "targs": (a,), "matrix": synth.haar_unitary(rng, 2)})
+            ops.append({"op": "unitary", "ctrls": (c,), "targs": (b,), "matrix": synth.haar_unitary(rng, 2)})
+        elif kind == 3:
+            w = int(rng.integers(2, 7))
+            t = tuple(int(x) for x in rng.permutation(N)[:w])
+            ops.append({"op": "gadget", "targs": t, "paulis": tuple(int(x) for x in rng.integers(1, 4, size=w)),
+                        "theta": rng.uniform(-3, 3)})
+        elif kind == 4:
+            ops.append({"op": "gadget", "targs": (a,), "paulis": (1,), "theta": rng.uniform(-3, 3)})
+            ops.append({"op": "gadget", "targs": (a,), "paulis": (3,), "theta": rng.uniform(-3, 3)})
+        else:
+            ops.append({"op": "unitary", "ctrls": (), "targs": (a, b), "matrix": synth.haar_unitary(rng, 4)})
+    psi = synth.random_state(rng, 1 << N)
+    want = oracle.run_ops(psi.copy(), ops)
+    circ = qs.Circuit(N, ops).compile(k, prec)
+    q = qs.Qureg(N, precision=prec).set_amps(psi)
+    circ.apply(q)
+    assert amp_err(q.get_amps(), want) < TOL[prec]
+    if circ.specialize():
+        q.set_amps(psi)
+        circ.apply(q)
+        assert amp_err(q.get_amps(), want) < TOL[prec]
