@@ -327,7 +327,9 @@ int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision);
  * run as up to eight child processes with sources written to a temporary
  * directory under $TMPDIR (default /tmp) that is removed afterwards (seconds
  * for hundreds of operators; code objects are cached per source for the
- * process).  Applying the circuit then
+ * process, and on disk in $QS_JIT_CACHE, default $TMPDIR/qs_jit_cache, used
+ * only if that directory belongs to the calling user and is not writable by
+ * others).  Applying the circuit then
  * launches these kernels; results equal those of the generic tile kernel.
  * *num_kernels (may be NULL) receives the number of specialised steps (0 for
  * a circuit without tile steps).  Recompiling or destroying the circuit

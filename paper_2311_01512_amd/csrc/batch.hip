@@ -557,19 +557,18 @@ __global__ __launch_bounds__(512) void k_batch_backward_reg(C2<R> *__restrict__ 
         }
     }
     int pend_phase = -1;   // phase whose rotation partials sit in red
+    // the finished phase's partials summed over the waves, one thread per
+    // operator and component (the reads complete before the barrier that
+    // precedes the next writes to red)
     auto flush = [&]() {
-        if (pend_phase >= 0 && t == 0) {
+        if (pend_phase >= 0) {
             const BPhase &D = phases[pend_phase];
-            for (int k = D.op_begin; k < D.op_end; k++) {
-                const DOp &op = ops[k];
+            for (int i = (int)t; i < 2 * (D.op_end - D.op_begin); i += (int)blockDim.x) {
+                const DOp &op = ops[D.op_begin + (i >> 1)];
                 if (op.grad < 0) continue;
-                double re = 0.0, im = 0.0;
-                for (int v2 = 0; v2 < nwaves; v2++) {
-                    re += red[op.slot][v2][0];
-                    im += red[op.slot][v2][1];
-                }
-                gpart[2 * (op.gpart + w.y)] = re;
-                gpart[2 * (op.gpart + w.y) + 1] = im;
+                double v = 0.0;
+                for (int v2 = 0; v2 < nwaves; v2++) v += red[op.slot][v2][i & 1];
+                gpart[2 * (op.gpart + w.y) + (i & 1)] = v;
             }
         }
         pend_phase = -1;

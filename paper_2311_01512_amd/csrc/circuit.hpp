@@ -102,6 +102,10 @@ int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev);
 size_t tile_mats_offset(const Pass &p);
 // Run-time specialisation of a compiled circuit's tile steps (jit.hip).
 int specialize_tiles(qs_circuit *c, int *num_kernels);
+// HIP sources -> code objects for `arch` (rtc.hip): from the process cache,
+// the disk cache, or the ROCm clang in parallel child processes.
+int compile_device_sources(const std::vector<std::string> &srcs, const std::string &arch,
+                           std::vector<std::vector<char>> &codes);
 void release_specialized(qs_circuit *c);
 
 Pass single_pass(const CircOp &op);
