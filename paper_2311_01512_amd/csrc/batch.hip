@@ -86,11 +86,47 @@ struct DTerm {
     double cre, cim;  // h_n i^{#Y}
 };
 
+// v moved across lanes by a DPP control (both 32-bit halves); lanes of rows
+// outside row_mask receive 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    int lo, hi;
+    __builtin_memcpy(&lo, &v, 4);
+    __builtin_memcpy(&hi, reinterpret_cast<const char *>(&v) + 4, 4);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false);
+    double r;
+    __builtin_memcpy(&r, &lo, 4);
+    __builtin_memcpy(reinterpret_cast<char *>(&r) + 4, &hi, 4);
+    return r;
+}
+
+// Sum over the active lanes of the wavefront, returned to every lane, with
+// data-parallel primitive moves instead of LDS permutes: within each row of
+// 16 lanes by quad permutes and mirrors (every lane ends with its row's
+// sum), then across rows by the row broadcasts of lanes 15 and 31 (the last
+// lane ends with the total).  Moves from inactive lanes bring 0, so for the
+// active sets used here, a prefix of 2^k lanes, the last active lane holds
+// the total and is read back.
 __device__ __forceinline__ double bwave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_move<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);       // row_half_mirror
+    v += dpp_move<0x140>(v);       // row_mirror
+    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    int lo, hi;
+    __builtin_memcpy(&lo, &v, 4);
+    __builtin_memcpy(&hi, reinterpret_cast<const char *>(&v) + 4, 4);
+    const int last = 63 - __builtin_clzll(__builtin_amdgcn_read_exec());
+    lo = __builtin_amdgcn_readlane(lo, last);
+    hi = __builtin_amdgcn_readlane(hi, last);
+    double r;
+    __builtin_memcpy(&r, &lo, 4);
+    __builtin_memcpy(reinterpret_cast<char *>(&r) + 4, &hi, 4);
+    return r;
 }
 
 // (re, im) summed over the block; valid in thread 0.
