@@ -436,8 +436,16 @@ __device__ __forceinline__ void reg_grad_pairs(const C2<R> (&x)[8], const C2<R> 
             p0 = f0;
             p1 = mk<R>(-f1.x, -f1.y);
         }
-        re += (double)l0.x * p0.x + (double)l0.y * p0.y + (double)l1.x * p1.x + (double)l1.y * p1.y;
-        im += (double)l0.x * p0.y - (double)l0.y * p0.x + (double)l1.x * p1.y - (double)l1.y * p1.x;
+        if constexpr (same_type<R, float>::value) {
+            // complex64 states: the pair's products in FP32 (relative error
+            // about 1e-7, below the states' own), the sums over lanes, waves
+            // and tiles in FP64
+            re += (double)(l0.x * p0.x + l0.y * p0.y + l1.x * p1.x + l1.y * p1.y);
+            im += (double)(l0.x * p0.y - l0.y * p0.x + l1.x * p1.y - l1.y * p1.x);
+        } else {
+            re += (double)l0.x * p0.x + (double)l0.y * p0.y + (double)l1.x * p1.x + (double)l1.y * p1.y;
+            im += (double)l0.x * p0.y - (double)l0.y * p0.x + (double)l1.x * p1.y - (double)l1.y * p1.x;
+        }
     }
     if constexpr (J == 0) asm volatile("; grad pairs 0");
     else if constexpr (J == 1) asm volatile("; grad pairs 1");
