@@ -197,3 +197,42 @@ def test_autotune_with_specialised_steps(qs):
     assert amp_err(q.get_amps(), oracle.run_ops(psi.copy(), ops)) < TOL["c64"]
     best2, _ = c.autotune(q, (0, 4))                 # the plain autotuner: no specialised steps
     assert c.specialized == 0 and best2 in (0, 4)
+
+
+@pytest.mark.parametrize("N,k,prec", [(9, 13, "c64"), (10, 10, "c64"), (12, 13, "c128"), (13, 13, "c64")])
+def test_specialized_single_tile_and_clipped_width(qs, N, k, prec):
+    """Tile width at or above the qubit count: one tile holds the whole state
+    (a single block walks it), the width is clipped to N."""
+    banner(f"specialised one-tile N={N} k={k} {prec}")
+    ops = synth.config2_circuit(num_qubits=N, num_gates=90, seed=77 + N)
+    rng = np.random.default_rng(77 + N)
+    psi = synth.random_state(rng, 1 << N)
+    c = qs.Circuit(N, ops).compile(k, prec)
+    q = qs.Qureg(N, precision=prec).set_amps(psi)
+    c.apply(q)
+    generic = q.get_amps()
+    assert c.specialize() > 0
+    q.set_amps(psi)
+    c.apply(q)
+    assert np.array_equal(q.get_amps(), generic)
+    assert amp_err(q.get_amps(), oracle.run_ops(psi.copy(), ops)) < TOL[prec]
+
+
+def test_specialized_density_circuit_c128(qs):
+    """Complex128 density circuit: superoperators in registers and sparse form
+    (no matrix cores in double precision)."""
+    banner("specialised density circuit c128")
+    N = 6
+    ops, _ = synth.config3_circuit(num_qubits=N, num_ops=60, seed=78, num_traced=3)
+    rng = np.random.default_rng(78)
+    psi = synth.random_state(rng, 1 << N)
+    rho = np.outer(psi, psi.conj()).reshape(-1, order="F")
+    c = qs.Circuit(N, ops, density=True).compile(11, "c128")
+    q = qs.Qureg(N, density=True, precision="c128").set_amps(rho)
+    c.apply(q)
+    generic = q.get_amps()
+    assert c.specialize() > 0
+    q.set_amps(rho)
+    c.apply(q)
+    assert np.array_equal(q.get_amps(), generic)
+    assert amp_err(q.get_amps(), oracle.run_ops(rho.copy(), ops, density=True)) < TOL["c128"]
