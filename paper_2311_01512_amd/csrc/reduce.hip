@@ -210,6 +210,148 @@ template <typename R> struct ExpecDM {
     }
 };
 
+// ---- Pauli sums on a statevector by tiles ----------------------------------------------
+// <psi|P_n|psi> = sum_i conj(a_i) beta_j a_j, j = i ^ x_n (the same pairing as
+// above).  A tile is a coset of V = span(e_0..e_{L-1}, w_0..w_{m-1}) where the
+// w_k are an echelon basis of the flip masks of several terms: with the tile
+// in LDS, each amplitude's partner j = i ^ x_n lies in the same tile for every
+// one of them, so one read of the state serves them all.  Tile element c
+// (a d-bit coordinate, d = L + m) sits at base ^ (c & (2^L - 1)) ^ xor of the
+// w_k over the set bits L + k of c; in these coordinates x_n is a d-bit
+// flip xc_n, and popc(j & yz_n) mod 2 is parity(base & yz_n) ^ parity(c_j & zc_n),
+// zc_n bit k = parity(coordinate vector k & yz_n).
+// For a Hermitian term the sum over i is real when parity(x_n & yz_n) = 0 and
+// imaginary otherwise (partners i, j contribute conjugate products whose signs
+// agree or differ), so a term accumulates one real number: the sum of
+// (-1)^{popc(j & yz_n)} Re or Im of conj(a_i) a_j; the host applies h_n i^{#Y}.
+// Block of 256 threads; thread t holds elements t + 256 u, u < E = 2^(d-8);
+// d <= 11 and L = 4 (runs of 16 contiguous amplitudes), so m = 7 masks per span.
+constexpr int kTileTerms = 8;
+constexpr int kTileBlocks = 1024;   // persistent blocks of one launch
+
+struct TileTermSet {
+    int count;
+    uint32_t kind;                  // bit n: term n sums Im (else Re)
+    uint32_t xl[kTileTerms];        // coordinate flip, thread bits (c & 255)
+    uint32_t xh[kTileTerms];        // coordinate flip, register bits (c >> 8)
+    uint32_t zl[kTileTerms];        // coordinate sign mask, thread bits
+    uint32_t zh[kTileTerms];        // coordinate sign mask, register bits
+    uint64_t yz[kTileTerms];        // sign mask of the term (tile base parity)
+};
+
+struct TileSpan {
+    InsertPlan plan;                // coset bases: zeros at the d pivot positions
+    uint64_t coord[8];              // offsets of coordinates 0..7 (thread bits)
+    uint64_t offu[8];               // offset of element 256 u
+};
+
+// One term's sum over the thread's elements of a tile, up to a sign that
+// the caller applies: partner coordinate (t + 256 u) ^ xc, and
+// (-1)^{popc((u ^ xh) & zh)} = (-1)^{popc(xh & zh)} (-1)^{popc(u & zh)}, the
+// second factor summed as a fold over the register bits (one sign per bit).
+template <bool IM, int E>
+__device__ __forceinline__ double term_sum(const double2 *__restrict__ tile, const double2 (&own)[E], uint32_t t,
+                                           uint32_t xc, uint32_t zh)
+{
+    double p[E];
+#pragma unroll
+    for (int u = 0; u < E; u++) {
+        const double2 v = tile[(t + 256u * u) ^ xc];
+        p[u] = IM ? own[u].x * v.y - own[u].y * v.x : own[u].x * v.x + own[u].y * v.y;
+    }
+#pragma unroll
+    for (int h = E / 2; h >= 1; h >>= 1) {
+        const double sg = (zh & (uint32_t)h) ? -1.0 : 1.0;
+#pragma unroll
+        for (int u = 0; u < h; u++) p[u] = fma(sg, p[u + h], p[u]);
+    }
+    return p[0];
+}
+
+template <typename R, int E>
+__global__ __launch_bounds__(256) void k_expec_tiles(const C2<R> *__restrict__ a, uint64_t num_tiles, TileSpan sp,
+                                                     TileTermSet ts, double *__restrict__ partials)
+{
+    __shared__ double2 tile[256 * E];    // FP64 copy: partners need no conversion per term
+    __shared__ double red[kTileTerms][4];
+    const uint32_t t = threadIdx.x;
+    uint64_t toff = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        if ((t >> k) & 1) toff ^= sp.coord[k];
+    double acc[kTileTerms];
+#pragma unroll
+    for (int n = 0; n < kTileTerms; n++) acc[n] = 0.0;
+
+    uint64_t g = blockIdx.x;
+    C2<R> x[E];
+    if (g < num_tiles) {
+        const uint64_t b0 = insert_zeros(g, sp.plan);
+#pragma unroll
+        for (int u = 0; u < E; u++) x[u] = a[b0 ^ sp.offu[u] ^ toff];
+    }
+    for (; g < num_tiles; g += gridDim.x) {
+        const uint64_t base = insert_zeros(g, sp.plan);
+        double2 own[E];
+#pragma unroll
+        for (int u = 0; u < E; u++) own[u] = make_double2((double)x[u].x, (double)x[u].y);
+        __syncthreads();    // the previous tile's reads are done
+#pragma unroll
+        for (int u = 0; u < E; u++) tile[t + 256 * u] = own[u];
+        __syncthreads();
+        // the next tile's loads go out before the sums
+        const uint64_t next = g + gridDim.x;
+#pragma unroll
+        for (int u = 0; u < E; u++) x[u] = mk<R>(R(0), R(0));
+        if (next < num_tiles) {
+            const uint64_t nb = insert_zeros(next, sp.plan);
+#pragma unroll
+            for (int u = 0; u < E; u++) x[u] = a[nb ^ sp.offu[u] ^ toff];
+        }
+        // t made opaque per tile: the partner addresses of every (term, u)
+        // are loop invariants that would otherwise stay live in registers
+        uint32_t tv = t;
+        asm volatile("" : "+v"(tv));
+#pragma unroll
+        for (int n = 0; n < kTileTerms; n++) {
+            if (n < ts.count) {
+                const uint32_t tp = tv ^ ts.xl[n];
+                const uint32_t xc = ts.xl[n] | (ts.xh[n] << 8);
+                uint32_t zh = ts.zh[n];      // likewise for the fold signs
+                asm volatile("" : "+s"(zh));
+                const double s = ((ts.kind >> n) & 1) ? term_sum<true, E>(tile, own, tv, xc, zh)
+                                                      : term_sum<false, E>(tile, own, tv, xc, zh);
+                const uint32_t par = (uint32_t)__popcll(base & ts.yz[n]) + (uint32_t)__popc(ts.xh[n] & ts.zh[n]) +
+                                     (uint32_t)__popc(tp & ts.zl[n]);
+                acc[n] += (par & 1) ? -s : s;
+            }
+        }
+    }
+    // per term: wave sums, then the four waves in order
+    const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int n = 0; n < kTileTerms; n++) {
+        if (n < ts.count) {
+            const double v = wave_sum(acc[n]);
+            if (lane == 0) red[n][wave] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)t < ts.count)
+        partials[(size_t)t * gridDim.x + blockIdx.x] = ((red[t][0] + red[t][1]) + red[t][2]) + red[t][3];
+}
+
+// Term n's block partials summed in block order into result[slot0 + n].
+__global__ __launch_bounds__(256) void k_finalize_terms(const double *__restrict__ partials, int blocks,
+                                                         double *__restrict__ result, int slot0)
+{
+    double re = 0.0, im = 0.0;
+    const double *p = partials + (size_t)blockIdx.x * blocks;
+    for (int b = threadIdx.x; b < blocks; b += blockDim.x) re += p[b];
+    block_sum2(re, im);
+    if (threadIdx.x == 0) result[slot0 + blockIdx.x] = re;
+}
+
 // ---- purity: Tr(rho^2) = sum_{k,l} rho[k][l] rho[l][k] ---------------------------------
 // Tiles of TS x TS entries: tile (kb, lb) with kb <= lb is read with k
 // fastest, its mirror with l fastest, the mirror goes through LDS so each
@@ -422,6 +564,175 @@ static int expec_sv(qs_qureg *q, const int *codes, const double *coeffs, int T, 
 }
 
 template <typename R>
+static void launch_expec_tiles(int E, int blocks, hipStream_t st, const C2<R> *amps, uint64_t num_tiles,
+                               const TileSpan &sp, const TileTermSet &ts, double *partials)
+{
+    if (E == 1) hipLaunchKernelGGL((k_expec_tiles<R, 1>), dim3(blocks), dim3(256), 0, st, amps, num_tiles, sp, ts, partials);
+    else if (E == 2) hipLaunchKernelGGL((k_expec_tiles<R, 2>), dim3(blocks), dim3(256), 0, st, amps, num_tiles, sp, ts, partials);
+    else if (E == 4) hipLaunchKernelGGL((k_expec_tiles<R, 4>), dim3(blocks), dim3(256), 0, st, amps, num_tiles, sp, ts, partials);
+    else hipLaunchKernelGGL((k_expec_tiles<R, 8>), dim3(blocks), dim3(256), 0, st, amps, num_tiles, sp, ts, partials);
+}
+
+// Tiled Pauli sum for N >= 8: spans of L low qubits plus up to d - L flip
+// masks (greedy, first fit over the distinct masks in ascending order), each
+// span's terms in launches of up to kTileTerms.
+template <typename R>
+static int expec_sv_tiles(qs_qureg *q, const int *codes, const double *coeffs, int T, double *re, double *im)
+{
+    const int N = q->num_qubits;
+    const int d = std::min(N, 11);
+    const int L = 4;
+    const int m = d - L;
+    const uint64_t lowmask = (1ULL << L) - 1ULL;
+    const cd eta[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+    std::vector<uint64_t> xs(T), yzs(T);
+    std::vector<cd> cs(T);
+    std::map<uint64_t, std::vector<int>> by_mask;
+    for (int t = 0; t < T; t++) {
+        uint64_t xy = 0, yz = 0;
+        int ny = 0;
+        for (int k = 0; k < N; k++) {
+            const int c = codes[(size_t)t * N + k];
+            if (c < 0 || c > 3) return fail(QS_E_ARG, "Pauli codes are 0..3");
+            if (c == 1 || c == 2) xy |= 1ULL << k;
+            if (c == 2 || c == 3) yz |= 1ULL << k;
+            if (c == 2) ny++;
+        }
+        xs[t] = xy;
+        yzs[t] = yz;
+        cs[t] = coeffs[t] * eta[ny & 3];
+        by_mask[xy].push_back(t);
+    }
+    std::vector<uint64_t> pending;
+    for (auto &kv : by_mask) pending.push_back(kv.first);
+
+    double acc_re = 0.0, acc_im = 0.0;
+    int slot = 0;
+    std::vector<int> slot_term;
+    auto flush = [&]() -> int {
+        if (slot == 0) return QS_OK;
+        QS_HIP(hipMemcpyAsync(q->h_result, q->d_result, sizeof(double) * slot, hipMemcpyDeviceToHost, q->stream));
+        QS_HIP(hipStreamSynchronize(q->stream));
+        for (int s = 0; s < slot; s++) {
+            const int t = slot_term[s];
+            const double v = q->h_result[s];
+            if (__builtin_popcountll(xs[t] & yzs[t]) & 1) {     // i v
+                acc_re -= cs[t].imag() * v;
+                acc_im += cs[t].real() * v;
+            } else {
+                acc_re += cs[t].real() * v;
+                acc_im += cs[t].imag() * v;
+            }
+        }
+        slot = 0;
+        slot_term.clear();
+        return QS_OK;
+    };
+
+    while (!pending.empty()) {
+        // reduced echelon basis of the high parts (pivot = highest bit)
+        std::vector<uint64_t> basis;
+        std::vector<uint64_t> chosen, rest;
+        for (uint64_t x : pending) {
+            uint64_t r = x & ~lowmask;
+            for (uint64_t b : basis)
+                if (r >> (63 - __builtin_clzll(b)) & 1) r ^= b;
+            if (r == 0) {
+                chosen.push_back(x);
+            } else if ((int)basis.size() < m) {
+                const int p = 63 - __builtin_clzll(r);
+                for (uint64_t &b : basis)
+                    if ((b >> p) & 1) b ^= r;
+                basis.push_back(r);
+                chosen.push_back(x);
+            } else {
+                rest.push_back(x);
+            }
+        }
+        pending.swap(rest);
+        // remaining coordinates L + k: pad with unit vectors on free qubits
+        std::vector<int> pivots;
+        for (uint64_t b : basis) pivots.push_back(63 - __builtin_clzll(b));
+        // (N >= d leaves enough free columns); clearing column b from the
+        // others keeps every pivot column in one basis vector only
+        for (int b = L; (int)basis.size() < m && b < N; b++) {
+            if (std::find(pivots.begin(), pivots.end(), b) != pivots.end()) continue;
+            for (uint64_t &v : basis) v &= ~(1ULL << b);
+            basis.push_back(1ULL << b);
+            pivots.push_back(b);
+        }
+        std::vector<int> order(m);
+        for (int k = 0; k < m; k++) order[k] = k;
+        std::sort(order.begin(), order.end(), [&](int i, int j) { return pivots[i] < pivots[j]; });
+        std::vector<uint64_t> coord(d);
+        std::vector<int> pos;
+        for (int k = 0; k < L; k++) { coord[k] = 1ULL << k; pos.push_back(k); }
+        for (int k = 0; k < m; k++) { coord[L + k] = basis[order[k]]; pos.push_back(pivots[order[k]]); }
+        std::sort(pos.begin(), pos.end());
+        TileSpan sp{};
+        sp.plan.n = d;
+        for (int k = 0; k < d; k++) sp.plan.low[k] = (1ULL << pos[k]) - 1ULL;
+        for (int k = 0; k < 8; k++) sp.coord[k] = coord[k];
+        const int E = 1 << (d - 8);
+        for (int u = 0; u < E; u++) {
+            uint64_t o = 0;
+            for (int k = 0; k < d - 8; k++)
+                if ((u >> k) & 1) o ^= coord[8 + k];
+            sp.offu[u] = o;
+        }
+        // coordinates of a flip mask and of a sign mask
+        auto flip_coord = [&](uint64_t x) {
+            uint32_t c = (uint32_t)(x & lowmask);
+            for (int k = 0; k < m; k++)
+                if ((x >> pivots[order[k]]) & 1) c |= 1u << (L + k);
+            return c;
+        };
+        auto sign_coord = [&](uint64_t yz) {
+            uint32_t c = 0;
+            for (int k = 0; k < d; k++)
+                if (__builtin_popcountll(coord[k] & yz) & 1) c |= 1u << k;
+            return c;
+        };
+        std::vector<int> terms;
+        for (uint64_t x : chosen)
+            for (int t : by_mask[x]) terms.push_back(t);
+        const uint64_t num_tiles = 1ULL << (N - d);
+        const int blocks = (int)std::min<uint64_t>(num_tiles, kTileBlocks);
+        for (size_t b0 = 0; b0 < terms.size(); b0 += kTileTerms) {
+            TileTermSet ts{};
+            ts.count = (int)std::min<size_t>(kTileTerms, terms.size() - b0);
+            if (slot + ts.count > kResultSlots) {
+                int rc = flush();
+                if (rc != QS_OK) return rc;
+            }
+            for (int n = 0; n < ts.count; n++) {
+                const int t = terms[b0 + n];
+                const uint32_t xc = flip_coord(xs[t]), zc = sign_coord(yzs[t]);
+                ts.xl[n] = xc & 255u;
+                ts.xh[n] = xc >> 8;
+                ts.zl[n] = zc & 255u;
+                ts.zh[n] = zc >> 8;
+                ts.yz[n] = yzs[t];
+                if (__builtin_popcountll(xs[t] & yzs[t]) & 1) ts.kind |= 1u << n;
+                slot_term.push_back(t);
+            }
+            const C2<R> *amps = (const C2<R> *)q->amps;
+            launch_expec_tiles<R>(E, blocks, q->stream, (const C2<R> *)q->amps, num_tiles, sp, ts, q->d_partials);
+            QS_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_finalize_terms, dim3(ts.count), dim3(256), 0, q->stream,
+                               (const double *)q->d_partials, blocks, q->d_result, slot);
+            QS_LAUNCH_CHECK();
+            slot += ts.count;
+        }
+    }
+    int rc = flush();
+    if (rc != QS_OK) return rc;
+    *re = acc_re;
+    *im = acc_im;
+    return QS_OK;
+}
+
+template <typename R>
 static int expec_dm(qs_qureg *q, const int *codes, const double *coeffs, int T, double *re, double *im)
 {
     const int N = q->num_qubits;
@@ -549,6 +860,9 @@ int qs_calc_expec_pauli_sum(const qs_qureg *cq, const int *paulis, const double 
         if (q->is_density)
             rc = q->precision == QS_C64 ? expec_dm<float>(q, paulis, coeffs, num_terms, &re, &im)
                                         : expec_dm<double>(q, paulis, coeffs, num_terms, &re, &im);
+        else if (q->num_qubits >= 8)
+            rc = q->precision == QS_C64 ? expec_sv_tiles<float>(q, paulis, coeffs, num_terms, &re, &im)
+                                        : expec_sv_tiles<double>(q, paulis, coeffs, num_terms, &re, &im);
         else
             rc = q->precision == QS_C64 ? expec_sv<float>(q, paulis, coeffs, num_terms, &re, &im)
                                         : expec_sv<double>(q, paulis, coeffs, num_terms, &re, &im);
