@@ -244,8 +244,14 @@ int qs_calc_partial_trace(const qs_qureg *in, const int *targs, int num_targs, q
  * Expectation of H = sum_t coeffs[t] (x)_q P(paulis[t*N + q]) (Sec. "Pauli
  * string expectation value").  paulis: num_terms * N codes, term-major then
  * qubit 0 first.  Density matrix: Tr(H rho) (Eq. "dens_expec_val_sum").
- * Statevector: <psi|H|psi>.  Accumulated in FP64; *out_im is the imaginary
- * part (zero up to rounding for Hermitian rho).  Either output may be NULL.
+ * Statevector: <psi|H|psi>.  On 8 or more qubits the terms are grouped
+ * into spans of up to 7 X/Y flip masks beyond the 4 lowest qubits, and the
+ * state is read once per span (tiles held on chip); each term sums its real
+ * or its imaginary part, whichever a Hermitian string can give, so *out_im
+ * is exactly 0 there.  Accumulated in FP64 in a fixed order (repeated calls
+ * give identical results); *out_im is the imaginary part (zero up to
+ * rounding for Hermitian rho).  Either output may be NULL.  Blocks until
+ * the value is on the host.
  */
 int qs_calc_expec_pauli_sum(const qs_qureg *q, const int *paulis, const double *coeffs,
                             int num_terms, double *out_re, double *out_im);
