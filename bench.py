@@ -175,6 +175,25 @@ def cpu_baseline(ops, n, budget_s):
                       f"complex128, {dt:.1f} s"}
 
 
+def copy_ceiling(torch, reps=5):
+    """A plain 2 GiB device copy (torch's copy kernel, 2 GiB read + 2 GiB
+    written per copy): the HBM rate a streaming kernel can reach in
+    practice on this GPU, for reading the roofline fraction against."""
+    src = torch.zeros(1 << 28, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    gbps = 2 * src.numel() * 8 * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbps
+
+
 def pmc_probe(args):
     import torch
     import synth
@@ -592,6 +611,10 @@ def main():
         "reductions_c128": bench_reductions(q128, torch, 16),
         "reductions_c64": bench_reductions(q64, torch, 8),
     }
+    copy_gbps = copy_ceiling(torch)
+    result["hbm_copy_ceiling"] = {"GBps": copy_gbps, "frac_of_peak": copy_gbps / 8000.0,
+                                  "roofline_achieved_over_copy": (result["roofline"]["achieved"] / copy_gbps
+                                                                  if result["roofline"]["unit"] == "GB/s" else None)}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_seconds)
     print(json.dumps(result), flush=True)
