@@ -529,55 +529,86 @@ void plan_tiles(qs_circuit *c, int T, int precision)
     // dense gates of 2-4 targets on the FP32 matrix cores (complex64 only)
     const bool mfma = precision == QS_C64 && T >= kRegBits + 6;
     const int lookahead = 512;
-    std::vector<char> placed(n_ops, 0);
     std::vector<OpMasks> masks(n_ops);
-    for (int i = 0; i < n_ops; i++) masks[i] = op_masks(c->ops[i]);
+    std::vector<std::vector<uint64_t>> needs(n_ops);
     for (int i = 0; i < n_ops; i++) {
-        if (placed[i]) continue;
-        const CircOp &first = c->ops[i];
-        // registers need a tile of more than kRegBits dimensions; controls
-        // beyond the 4 a tile operator carries, or gates of more than 3
-        // targets, run as passes of their own
-        if (T <= kRegBits || !absorbable(first, mfma) || first.ctrls.size() > 4) {
-            placed[i] = 1;
-            c->passes.push_back(single_pass(first));
-            continue;
-        }
-        Echelon E;
+        masks[i] = op_masks(c->ops[i]);
+        needs[i] = needed_vectors(c->ops[i]);
+    }
+    // Admission rules for one step.  Rule g < 0: one greedy sweep over the
+    // window.  Rule g >= 0: a first sweep admits only operators that grow the
+    // span by at most g dimensions (the step's first operator always), then
+    // the greedy sweep.  Either way an operator joins a step only if it
+    // commutes with every earlier operator left out, so it also commutes
+    // with every member placed after it in circuit order: the member list
+    // is a valid order of application.
+    auto build_step = [&](int i, int g, std::vector<char> &placed, Echelon &E,
+                          std::vector<const CircOp *> &members) {
         for (int b = 0; b < C; b++) E.add(1ULL << b);
-        std::vector<const CircOp *> members;
-        // operators the step leaves out: a later operator joins only if it
-        // commutes with every one of them
-        std::vector<int> skipped;
-        for (int j = i; j < n_ops && j < i + lookahead; j++) {
-            if (placed[j]) continue;
-            const CircOp &op = c->ops[j];
-            bool free = true;
-            for (int k : skipped)
-                if (!ops_commute(masks[j], masks[k])) {
-                    free = false;
-                    break;
+        for (int sweep = g < 0 ? 1 : 0; sweep < 2; sweep++) {
+            // operators the step leaves out: a later operator joins only if
+            // it commutes with every one of them
+            std::vector<int> skipped;
+            for (int j = i; j < n_ops && j < i + lookahead; j++) {
+                if (placed[j]) continue;
+                const CircOp &op = c->ops[j];
+                bool free = true;
+                for (int k : skipped)
+                    if (!ops_commute(masks[j], masks[k])) {
+                        free = false;
+                        break;
+                    }
+                if (!free) {
+                    skipped.push_back(j);
+                    continue;
                 }
-            if (!free) {
-                skipped.push_back(j);
+                const int dim = E.dim_with(needs[j]);
+                const bool fits = absorbable(op, mfma) && op.ctrls.size() <= 4 && dim <= T &&
+                                  (sweep == 1 || j == i || dim - E.dim() <= g);
+                if (fits) {
+                    for (uint64_t x : needs[j]) E.add(x);
+                    members.push_back(&op);
+                    placed[j] = 1;
+                } else {
+                    skipped.push_back(j);
+                }
+            }
+        }
+    };
+    // one plan per rule, the same rule for every step
+    auto plan = [&](int rule, std::vector<Pass> &out) {
+        std::vector<char> placed(n_ops, 0);
+        for (int i = 0; i < n_ops; i++) {
+            if (placed[i]) continue;
+            const CircOp &first = c->ops[i];
+            // registers need a tile of more than kRegBits dimensions; controls
+            // beyond the 4 a tile operator carries, or gates of more than 3
+            // targets, run as passes of their own
+            if (T <= kRegBits || !absorbable(first, mfma) || first.ctrls.size() > 4) {
+                placed[i] = 1;
+                out.push_back(single_pass(first));
                 continue;
             }
-            const std::vector<uint64_t> need = needed_vectors(op);
-            if (absorbable(op, mfma) && op.ctrls.size() <= 4 && E.dim_with(need) <= T) {
-                for (uint64_t x : need) E.add(x);
-                members.push_back(&op);
-                placed[j] = 1;
-            } else {
-                skipped.push_back(j);
-            }
+            Echelon E;
+            std::vector<const CircOp *> members;
+            build_step(i, rule, placed, E, members);
+            // fill the tile to T dimensions with the lowest free qubits: longer
+            // contiguous runs, fewer and larger tiles
+            for (int b = C; b < N && E.dim() < T; b++) E.add(1ULL << b);
+            Pass p{};
+            encode_step(p, E, members, mfma);
+            out.push_back(std::move(p));
         }
-        // fill the tile to T dimensions with the lowest free qubits: longer
-        // contiguous runs, fewer and larger tiles
-        for (int b = C; b < N && E.dim() < T; b++) E.add(1ULL << b);
-        Pass p{};
-        encode_step(p, E, members, mfma);
-        c->passes.push_back(std::move(p));
+    };
+    // the plan with the fewest passes wins (ties to the plain greedy)
+    std::vector<Pass> best;
+    plan(-1, best);
+    for (int rule : {0, 1}) {
+        std::vector<Pass> alt;
+        plan(rule, alt);
+        if (alt.size() < best.size()) best.swap(alt);
     }
+    for (Pass &p : best) c->passes.push_back(std::move(p));
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

@@ -133,6 +133,33 @@ def test_28_qubits_single_ops_every_kernel(qs):
     torch.cuda.empty_cache()
 
 
+def test_28_qubit_circuit_width13_plan(qs):
+    """The 500-gate 28-qubit circuit that the benchmark times, in 2^13 tiles
+    with specialised steps (complex64).  Its plan comes from a two-sweep
+    admission rule (57 steps, one fewer than the plain greedy), whose steps
+    list members out of circuit order where operators commute.  The result
+    is checked against the plain per-gate complex128 path, which has no
+    planner: a wrong order of two operators would show as an O(1) error."""
+    import torch
+    banner("28-qubit circuit, 2^13 tiles, specialised")
+    N = 28
+    ops = synth.config2_circuit(num_qubits=N, num_gates=500)
+    fused = qs.Circuit(N, ops).compile(13, "c64")
+    assert fused.stats()["num_passes"] <= 57
+    assert fused.specialize() > 0
+    q64 = qs.Qureg(N, precision="c64").init_hashed(9)
+    q128 = qs.Qureg(N, precision="c128").init_hashed(9)
+    fused.apply(q64)
+    qs.Circuit(N, ops).compile(0, "c128").apply(q128)
+    q64.sync()
+    q128.sync()
+    err = (q64.tensor.to(torch.complex128) - q128.tensor).abs().max().item()
+    scale = q128.tensor.abs().max().item()
+    assert err < 1e-5 * scale, (err, scale)
+    del q64, q128
+    torch.cuda.empty_cache()
+
+
 def test_28_qubit_pauli_sum_by_term(qs):
     """The 20-term Pauli sum at full size (3 tile spans of flip masks, as
     timed) against a second route: each term applied to a copy by the
