@@ -196,8 +196,9 @@ int qs_circuit_create_density(int num_qubits, qs_circuit **out)
 int qs_circuit_destroy(qs_circuit *c)
 {
     if (!c) return QS_OK;
-    release_specialized(c);
+    release_specialized(c);   // waits for queued passes first
     if (c->dev) (void)hipFree(c->dev);
+    for (auto &u : c->uses) (void)hipEventDestroy((hipEvent_t)u.second);
     delete c;
     return QS_OK;
 }
@@ -340,6 +341,7 @@ int qs_circuit_compile(qs_circuit *c, int fuse_k, int precision)
         total += (b + 255) & ~size_t(255);
     }
     if (c->dev) {
+        wait_circuit_uses(c);
         (void)hipFree(c->dev);
         c->dev = nullptr;
     }
@@ -423,6 +425,24 @@ uint64_t circuit_fingerprint(const qs_circuit *c)
 
 int circuit_num_qubits(const qs_circuit *c) { return c->num_qubits; }
 
+int note_circuit_use(qs_circuit *c, hipStream_t s)
+{
+    hipEvent_t ev = nullptr;
+    for (auto &u : c->uses)
+        if (u.first == (void *)s) ev = (hipEvent_t)u.second;
+    if (!ev) {
+        QS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        c->uses.emplace_back((void *)s, (void *)ev);
+    }
+    QS_HIP(hipEventRecord(ev, s));
+    return QS_OK;
+}
+
+void wait_circuit_uses(qs_circuit *c)
+{
+    for (auto &u : c->uses) (void)hipEventSynchronize((hipEvent_t)u.second);
+}
+
 }  // namespace qs
 
 extern "C" {
@@ -487,7 +507,7 @@ int qs_apply_circuit_passes(qs_qureg *q, qs_circuit *c, int first, int count)
         }
         if (rc != QS_OK) return rc;
     }
-    return QS_OK;
+    return count > 0 ? note_circuit_use(c, q->stream) : QS_OK;
 }
 
 }  // extern "C"

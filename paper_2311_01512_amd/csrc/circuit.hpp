@@ -107,6 +107,10 @@ int specialize_tiles(qs_circuit *c, int *num_kernels);
 int compile_device_sources(const std::vector<std::string> &srcs, const std::string &arch,
                            std::vector<std::vector<char>> &codes);
 void release_specialized(qs_circuit *c);
+// Records that passes of c were queued on stream s (after them), and waits
+// for every such use to finish (before tables or kernels are released).
+int note_circuit_use(qs_circuit *c, hipStream_t s);
+void wait_circuit_uses(qs_circuit *c);
 
 Pass single_pass(const CircOp &op);
 
@@ -125,4 +129,7 @@ struct qs_circuit {
     size_t dev_bytes = 0;
     int device = -1;
     std::vector<void *> jit_modules;   // modules of the specialised tile-step kernels
+    // one event per stream the circuit's passes were queued on, recorded after
+    // the last of them: tables and kernels are released only once they passed
+    std::vector<std::pair<void *, void *>> uses;   // (hipStream_t, hipEvent_t)
 };

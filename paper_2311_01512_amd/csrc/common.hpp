@@ -15,9 +15,16 @@
 
 namespace qs {
 
+// Every entry point bounds the number of positions it splices before it gets
+// here; a longer list yields an empty plan (n = -1, which inserts nothing)
+// instead of writing past the fixed arrays.
 inline InsertPlan make_insert_plan(std::vector<int> qubits)
 {
     InsertPlan p{};
+    if (qubits.size() > (size_t)kMaxInsert) {
+        p.n = -1;
+        return p;
+    }
     std::vector<int> s = qubits;
     for (size_t i = 1; i < s.size(); i++)       // insertion sort, tiny lists
         for (size_t j = i; j > 0 && s[j - 1] > s[j]; j--) std::swap(s[j - 1], s[j]);
@@ -99,6 +106,12 @@ int stage_matrix(qs_qureg *q, const void *host, size_t bytes, const void **dev);
 
 // Device reduction helpers, defined in reduce.hip.
 int finish_reduction(qs_qureg *q, int blocks, int width, double *out);
+// Doubles of q->d_partials that the Pauli-sum expectation value uses at most.
+constexpr size_t kExpecPartials = 2 * (size_t)kReduceBlocks;
+// The Pauli-sum expectation value of qs_calc_expec_pauli_sum on q, whose
+// d_partials / d_result / h_result serve as its scratch.
+int expec_pauli_sum(qs_qureg *q, const int *paulis, const double *coeffs, int num_terms, double *out_re,
+                    double *out_im);
 
 // ---- dense gates (gates.hip) ---------------------------------------------------
 

@@ -305,6 +305,7 @@ std::vector<std::string> specialized_sources(const qs_circuit *c, int chunks, si
 
 void release_specialized(qs_circuit *c)
 {
+    if (!c->jit_modules.empty()) wait_circuit_uses(c);   // queued steps may still run these kernels
     for (auto &p : c->passes) {
         p.jit_fn = nullptr;
         p.jit_grid = 0;

@@ -37,6 +37,22 @@ int stage_matrix(qs_qureg *q, const void *host, size_t bytes, const void **dev)
 {
     const size_t aligned = (bytes + 255) & ~size_t(255);
     if (aligned > q->mat_ring_bytes) return fail(QS_E_ARG, "matrix larger than the staging ring");
+    if (!q->d_mat_ring) {
+        // allocated on the first matrix too large for kernel arguments
+        if (hipMalloc(&q->d_mat_ring, q->mat_ring_bytes) != hipSuccess) {
+            q->d_mat_ring = nullptr;
+            (void)hipGetLastError();
+            return fail(QS_E_ALLOC, "allocation of the matrix staging ring failed");
+        }
+        if (hipHostMalloc(&q->h_mat_ring, q->mat_ring_bytes, hipHostMallocDefault) != hipSuccess) {
+            q->h_mat_ring = nullptr;
+            (void)hipGetLastError();
+            (void)hipFree(q->d_mat_ring);
+            q->d_mat_ring = nullptr;
+            return fail(QS_E_ALLOC, "allocation of the pinned matrix staging ring failed");
+        }
+        q->mat_ring_head = 0;
+    }
     if (q->mat_ring_head + aligned > q->mat_ring_bytes) {
         // Wrapping: earlier copies out of the pinned ring must have finished.
         QS_HIP(hipStreamSynchronize(q->stream));
@@ -173,9 +189,7 @@ int qs_create_qureg(int num_qubits, int is_density, int precision, void *device_
     }
     if (hipMalloc(&q->d_partials, sizeof(double) * 2 * kReduceBlocks * 4) != hipSuccess ||
         hipMalloc(&q->d_result, sizeof(double) * kResultSlots) != hipSuccess ||
-        hipHostMalloc(&q->h_result, sizeof(double) * kResultSlots, hipHostMallocDefault) != hipSuccess ||
-        hipMalloc(&q->d_mat_ring, kMatRingBytes) != hipSuccess ||
-        hipHostMalloc(&q->h_mat_ring, kMatRingBytes, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&q->h_result, sizeof(double) * kResultSlots, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         return cleanup(QS_E_ALLOC, "scratch allocation failed");
     }

@@ -396,30 +396,93 @@ __global__ __launch_bounds__(256) void k_purity(const C2<R> *__restrict__ a, int
 }
 
 // ---- partial trace (Eq. "partial_trace_reduced_amp_def") -------------------------------
-struct SpreadBits {
-    int n;
-    uint64_t m[kMaxInsert];   // bit p of v -> (1 << t_p) | (1 << (t_p + N))
+//
+// The entries that the trace reads are those whose bit t + N equals bit t for
+// every traced qubit t.  They are indexed by L, the Choi index with the bits
+// t + N removed (2N - n bits): the address of L is L with zeros spliced in at
+// the positions t + N, each then set to the bit t of L.  The low N bits of the
+// address are those of L, so a wavefront whose lanes take the 6 lowest bits of
+// L reads 64 consecutive entries.  Lanes that differ only in traced bits below
+// 6 belong to the same output and are summed by shuffles; the traced bits from
+// 6 up are the thread's loop (split over S waves of the block, whose partial
+// sums meet in LDS, when the loop is long and the threads few).  Removing the
+// traced positions from L gives the output index (kept row bits, then kept
+// column bits, each in qubit order).
+struct PTracePlan {
+    InsertPlan top;       // zeros at the positions t + N (address space)
+    InsertPlan hi;        // zeros at the traced positions >= 6 (L space): spreads the thread number
+    uint64_t lo_mask;     // traced positions < 6 (lane bits)
+    uint64_t slice_mask;  // the lowest log2(S) traced positions >= 6: which part of the loop a wave takes
+    uint64_t loop_mask;   // the other traced positions >= 6: the loop of every thread
+    uint64_t num_threads; // 2^(2N - n - n_hi)
+    int N;
+    int slices;           // S, waves per lane group
+    int groups;           // lane groups of 64 threads per block
 };
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_partial_trace(const C2<R> *__restrict__ in, C2<R> *__restrict__ out,
-                                                        uint64_t n_out, InsertPlan plan, SpreadBits sp)
+__global__ __launch_bounds__(1024) void k_partial_trace(const C2<R> *__restrict__ in, C2<R> *__restrict__ out,
+                                                        PTracePlan p)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t nv = 1ULL << sp.n;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_out; i += stride) {
-        const uint64_t g0 = insert_zeros(i, plan);
-        double re = 0.0, im = 0.0;
-        for (uint64_t v = 0; v < nv; v++) {
-            uint64_t g = g0;
-            for (int p = 0; p < sp.n; p++)
-                if ((v >> p) & 1) g |= sp.m[p];
-            const C2<R> x = in[g];
-            re += x.x;
-            im += x.y;
+    __shared__ double s_part[16][64][2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slice = wave % p.slices, group = wave / p.slices;
+    const uint64_t T = ((uint64_t)blockIdx.x * p.groups + group) * 64 + lane;
+    const bool live = T < p.num_threads;
+    double re = 0.0, im = 0.0;
+    if (live) {
+        const uint64_t L = insert_zeros(T, p.hi);
+        uint64_t base = insert_zeros(L, p.top);
+        uint64_t lo = L & p.lo_mask;
+        base |= lo << p.N;
+        // this wave's fixed slice bits: the slice number deposited in slice_mask
+        uint64_t sl = 0;
+        {
+            uint64_t m = p.slice_mask;
+            for (int b = 0; m; b++, m &= m - 1)
+                if ((slice >> b) & 1) sl |= m & (~m + 1);
         }
-        out[i] = mk<R>((R)re, (R)im);
+        base |= sl | (sl << p.N);
+        // every subset s of loop_mask in increasing order: s' = ((s | ~M) + 1) & M
+        uint64_t s = 0;
+        const uint64_t M = p.loop_mask;
+        const uint64_t count = 1ULL << __popcll(M);
+#pragma unroll 8
+        for (uint64_t j = 0; j < count; j++) {
+            const C2<R> x = in[base | s | (s << p.N)];
+            re += (double)x.x;
+            im += (double)x.y;
+            s = ((s | ~M) + 1) & M;
+        }
     }
+    if (p.slices > 1) {
+        s_part[wave][lane][0] = re;
+        s_part[wave][lane][1] = im;
+        __syncthreads();
+        if (slice == 0) {
+            re = 0.0;
+            im = 0.0;
+            for (int k = 0; k < p.slices; k++) {
+                re += s_part[wave + k][lane][0];
+                im += s_part[wave + k][lane][1];
+            }
+        }
+    }
+    if (slice != 0) return;   // wave-uniform
+    // sum over the traced lane bits, lowest first
+#pragma unroll
+    for (int b = 0; b < 6; b++)
+        if ((p.lo_mask >> b) & 1) {
+            re += __shfl_xor(re, 1 << b, 64);
+            im += __shfl_xor(im, 1 << b, 64);
+        }
+    if (!live || (lane & p.lo_mask)) return;
+    uint64_t o = 0;
+    int w = 0;
+    for (int b = 0; b < 6; b++)
+        if (!((p.lo_mask >> b) & 1)) o |= (uint64_t)((lane >> b) & 1) << w++;
+    o |= (T >> 6) << w;
+    out[o] = mk<R>((R)re, (R)im);
 }
 
 // ---- host drivers ----------------------------------------------------------------------
@@ -792,16 +855,67 @@ template <typename R>
 static int partial_trace(const qs_qureg *in, const std::vector<int> &t, qs_qureg *out)
 {
     const int N = in->num_qubits, n = (int)t.size();
-    std::vector<int> both(t);
-    for (int x : t) both.push_back(x + N);
-    InsertPlan plan = make_insert_plan(both);
-    SpreadBits sp{};
-    sp.n = n;
-    for (int p = 0; p < n; p++) sp.m[p] = (1ULL << t[p]) | (1ULL << (t[p] + N));
-    const uint64_t n_out = out->num_amps;
-    hipLaunchKernelGGL(k_partial_trace<R>, dim3(grid_for(n_out, 256)), dim3(256), 0, in->stream,
-                       (const C2<R> *)in->amps, (C2<R> *)out->amps, n_out, plan, sp);
+    PTracePlan p{};
+    std::vector<int> top, hi;
+    for (int x : t) {
+        top.push_back(x + N);
+        if (x >= 6) hi.push_back(x); else p.lo_mask |= 1ULL << x;
+    }
+    std::sort(hi.begin(), hi.end());
+    p.top = make_insert_plan(top);
+    p.hi = make_insert_plan(hi);
+    p.N = N;
+    const int n_hi = (int)hi.size();
+    p.num_threads = 1ULL << (2 * N - n - n_hi);
+    // split the loop over up to 16 waves while the threads are few
+    int slices = 1, sbits = 0;
+    while (slices < 16 && sbits < n_hi && p.num_threads * (uint64_t)slices < (1ULL << 17)) {
+        slices *= 2;
+        sbits++;
+    }
+    for (int k = 0; k < n_hi; k++) {
+        if (k < sbits) p.slice_mask |= 1ULL << hi[k];
+        else p.loop_mask |= 1ULL << hi[k];
+    }
+    p.slices = slices;
+    const int waves = std::max(4, slices);
+    p.groups = waves / slices;
+    const uint64_t lane_groups = (p.num_threads + 63) / 64;
+    const uint64_t blocks = (lane_groups + p.groups - 1) / p.groups;
+    if (blocks > 0xFFFFFFFFull / (64ull * waves)) return fail(QS_E_ARG, "partial trace too large for one launch");
+    hipLaunchKernelGGL(k_partial_trace<R>, dim3((unsigned)blocks), dim3(64 * waves), 0, in->stream,
+                       (const C2<R> *)in->amps, (C2<R> *)out->amps, p);
     QS_LAUNCH_CHECK();
+    (void)out;
+    return QS_OK;
+}
+
+// Pauli sum on a statevector (tiles for N >= 8, else pairs per flip mask)
+// or a density matrix.  Scratch: q->d_partials (at most kExpecPartials
+// doubles: 2 per reduction block, or one per tile block and term) and
+// q->d_result (kResultSlots doubles); no staging of matrices.
+static_assert(kExpecPartials >= 2 * (size_t)kReduceBlocks, "reduction partials exceed the bound");
+static_assert(kExpecPartials >= (size_t)kTileBlocks * kTileTerms, "tile partials exceed the bound");
+int expec_pauli_sum(qs_qureg *q, const int *paulis, const double *coeffs, int num_terms, double *out_re,
+                           double *out_im)
+{
+    if (num_terms < 0 || (num_terms > 0 && (!paulis || !coeffs))) return fail(QS_E_ARG, "bad Pauli sum");
+    double re = 0.0, im = 0.0;
+    int rc = QS_OK;
+    if (num_terms > 0) {
+        if (q->is_density)
+            rc = q->precision == QS_C64 ? expec_dm<float>(q, paulis, coeffs, num_terms, &re, &im)
+                                        : expec_dm<double>(q, paulis, coeffs, num_terms, &re, &im);
+        else if (q->num_qubits >= 8)
+            rc = q->precision == QS_C64 ? expec_sv_tiles<float>(q, paulis, coeffs, num_terms, &re, &im)
+                                        : expec_sv_tiles<double>(q, paulis, coeffs, num_terms, &re, &im);
+        else
+            rc = q->precision == QS_C64 ? expec_sv<float>(q, paulis, coeffs, num_terms, &re, &im)
+                                        : expec_sv<double>(q, paulis, coeffs, num_terms, &re, &im);
+    }
+    if (rc != QS_OK) return rc;
+    if (out_re) *out_re = re;
+    if (out_im) *out_im = im;
     return QS_OK;
 }
 
@@ -853,24 +967,7 @@ int qs_calc_expec_pauli_sum(const qs_qureg *cq, const int *paulis, const double 
 {
     qs_qureg *q = const_cast<qs_qureg *>(cq);
     if (!q) return fail(QS_E_ARG, "null qureg");
-    if (num_terms < 0 || (num_terms > 0 && (!paulis || !coeffs))) return fail(QS_E_ARG, "bad Pauli sum");
-    double re = 0.0, im = 0.0;
-    int rc = QS_OK;
-    if (num_terms > 0) {
-        if (q->is_density)
-            rc = q->precision == QS_C64 ? expec_dm<float>(q, paulis, coeffs, num_terms, &re, &im)
-                                        : expec_dm<double>(q, paulis, coeffs, num_terms, &re, &im);
-        else if (q->num_qubits >= 8)
-            rc = q->precision == QS_C64 ? expec_sv_tiles<float>(q, paulis, coeffs, num_terms, &re, &im)
-                                        : expec_sv_tiles<double>(q, paulis, coeffs, num_terms, &re, &im);
-        else
-            rc = q->precision == QS_C64 ? expec_sv<float>(q, paulis, coeffs, num_terms, &re, &im)
-                                        : expec_sv<double>(q, paulis, coeffs, num_terms, &re, &im);
-    }
-    if (rc != QS_OK) return rc;
-    if (out_re) *out_re = re;
-    if (out_im) *out_im = im;
-    return QS_OK;
+    return expec_pauli_sum(q, paulis, coeffs, num_terms, out_re, out_im);
 }
 
 int qs_calc_inner_product(const qs_qureg *ca, const qs_qureg *cb, double *out_re, double *out_im)
@@ -899,6 +996,7 @@ int qs_calc_partial_trace(const qs_qureg *in, const int *targs, int num_targs, q
     if (in->precision != out->precision) return fail(QS_E_TYPE, "precisions differ");
     if (num_targs < 1 || num_targs >= in->num_qubits || !targs)
         return fail(QS_E_ARG, "trace out between 1 and N-1 qubits");
+    if (num_targs > kMaxInsert) return fail(QS_E_ARG, "too many traced qubits");
     if (out->num_qubits != in->num_qubits - num_targs)
         return fail(QS_E_ARG, "output must have N - n qubits");
     if (in->amps == out->amps) return fail(QS_E_ARG, "input and output must not alias");
