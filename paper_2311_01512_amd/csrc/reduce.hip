@@ -447,8 +447,22 @@ __global__ __launch_bounds__(1024) void k_partial_trace(const C2<R> *__restrict_
         uint64_t s = 0;
         const uint64_t M = p.loop_mask;
         const uint64_t count = 1ULL << __popcll(M);
-#pragma unroll 8
-        for (uint64_t j = 0; j < count; j++) {
+        uint64_t j = 0;
+        // eight loads in flight before their sums (same order of additions)
+        for (; j + 8 <= count; j += 8) {
+            C2<R> x[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                x[k] = in[base | s | (s << p.N)];
+                s = ((s | ~M) + 1) & M;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                re += (double)x[k].x;
+                im += (double)x[k].y;
+            }
+        }
+        for (; j < count; j++) {
             const C2<R> x = in[base | s | (s << p.N)];
             re += (double)x.x;
             im += (double)x.y;
