@@ -256,6 +256,28 @@ int qs_calc_partial_trace(const qs_qureg *in, const int *targs, int num_targs, q
 int qs_calc_expec_pauli_sum(const qs_qureg *q, const int *paulis, const double *coeffs,
                             int num_terms, double *out_re, double *out_im);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the value
+ * of qs_calc_expec_pauli_sum computed on a caller's device buffer with no
+ * qureg and no allocation of any kind.  amps: device pointer of the current
+ * device holding 2^num_qubits (statevector) or 2^(2 num_qubits) (density
+ * matrix, Choi vector) interleaved amplitudes of the given precision,
+ * owned by the caller; hip_stream: the hipStream_t the work is ordered on
+ * (NULL = null stream).  paulis, coeffs, num_terms, out_re, out_im as for
+ * qs_calc_expec_pauli_sum; the result and its summation order are the same.
+ * Scratch: a library-owned static device array of 256 KiB + 512 B per GPU,
+ * which every size fits (the reductions cap their partial sums), kept until
+ * the process ends.  All calls on one GPU share it: calls that overlap on
+ * one GPU race.  Errors: QS_E_ARG for a null or non-device pointer, memory
+ * of another device, a bad precision or qubit count (index bits <= 62), or
+ * a malformed Pauli sum; QS_E_HIP if a HIP call fails.  Blocks until the
+ * value is on the host.
+ */
+int qs_calc_expec_pauli_sum_noalloc(const void *amps, int num_qubits, int is_density, int precision,
+                                    void *hip_stream, const int *paulis, const double *coeffs,
+                                    int num_terms, double *out_re, double *out_im);
+
 /* Probability that measuring `qubit` gives `outcome` (0/1): the sum of |a_i|^2
  * over i with that bit (Born rule), or of Re rho[k][k] for a density matrix.
  * Not renormalised.  FP64 accumulation. */

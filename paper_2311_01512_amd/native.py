@@ -62,6 +62,7 @@ _SIGS = {
     "qs_apply_kraus_map": [_P, _P, _I, _P, _I],
     "qs_calc_partial_trace": [_P, _P, _I, _P],
     "qs_calc_expec_pauli_sum": [_P, _P, _P, _I, _PD, _PD],
+    "qs_calc_expec_pauli_sum_noalloc": [_P, _I, _I, _I, _P, _P, _P, _I, _PD, _PD],
     "qs_calc_prob_of_outcome": [_P, _I, _I, _PD],
     "qs_calc_total_prob": [_P, _PD],
     "qs_calc_trace": [_P, _PD, _PD],
@@ -281,6 +282,18 @@ def qs_calc_expec_pauli_sum(q, paulis, coeffs):
     re, im = C.c_double(), C.c_double()
     check(lib.qs_calc_expec_pauli_sum(q, ptr(p), ptr(c), c.size, C.byref(re), C.byref(im)),
           "qs_calc_expec_pauli_sum")
+    return complex(re.value, im.value)
+
+
+def qs_calc_expec_pauli_sum_noalloc(amps_ptr, num_qubits, is_density, precision, stream, paulis, coeffs):
+    p = np.ascontiguousarray(np.asarray(paulis, dtype=np.int32))
+    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+    if p.size != c.size * num_qubits:
+        raise ValueError("need num_terms * num_qubits Pauli codes")
+    re, im = C.c_double(), C.c_double()
+    check(lib.qs_calc_expec_pauli_sum_noalloc(amps_ptr, num_qubits, int(is_density), precision, stream, ptr(p),
+                                              ptr(c), c.size, C.byref(re), C.byref(im)),
+          "qs_calc_expec_pauli_sum_noalloc")
     return complex(re.value, im.value)
 
 
