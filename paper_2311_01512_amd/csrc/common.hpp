@@ -148,6 +148,15 @@ int mfma_preference();
 // Upper bound on the MFMA kernel's grid for a k-target gate.
 uint64_t mfma_block_cap(int k);
 
+// Tile-step grids for tiles of 2^tile_d amplitudes: resident blocks each
+// walking a run of consecutive tiles, resident blocks walking tiles
+// blockIdx + k gridDim, or one block per tile.
+enum { kTileGridChunk = 0, kTileGridStride = 1, kTileGridPerTile = 2 };
+int tile_grid_policy(int tile_d);
+// Waves per SIMD that specialised tile steps are compiled for (bounds their
+// registers).
+int step_waves_per_eu(bool f32);
+
 // Number of lowest qubits every tile step holds (a tile is read in runs of
 // 2^this amplitudes).
 int tile_low_qubits(int precision);

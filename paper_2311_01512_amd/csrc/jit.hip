@@ -217,8 +217,9 @@ std::string step_kernel(const Pass &p, int index, bool f32, size_t max_lds)
     // four for complex128): straight-line code would otherwise hoist loads
     // and spend registers on them
     o << "extern \"C\" __global__ __launch_bounds__(" << block << ") __attribute__((amdgpu_waves_per_eu("
-      << (f32 ? 6 : 4) << "))) void qs_step_" << index << "(" << c2
-      << " *__restrict__ a, unsigned long long num_tiles, const " << c2 << " *__restrict__ mats)\n{\n";
+      << step_waves_per_eu(f32) << "))) void qs_step_" << index << "(" << c2
+      << " *__restrict__ a, unsigned long long num_tiles, const " << c2
+      << " *__restrict__ mats, int chunk)\n{\n";
     o << "    using R = " << (f32 ? "float" : "double") << ";\n";
     o << "    extern __shared__ unsigned char lds_raw[];\n";
     std::vector<int> piv = p.pivots;
@@ -258,7 +259,7 @@ std::string step_kernel(const Pass &p, int index, bool f32, size_t max_lds)
         o << "        __syncthreads();\n    }\n";
     }
     o << "    qs::tile_walk<R>(a, num_tiles, plan, P0, P" << p.phases.size() - 1 << ", " << lb
-      << ", [&](qs::C2<R> (&x)[qs::kRegs], uint64_t base) {\n";
+      << ", chunk != 0, [&](qs::C2<R> (&x)[qs::kRegs], uint64_t base) {\n";
     o << "        uint32_t tau = qs::tau_of(threadIdx.x, P0);\n";
     for (size_t k = 0; k < p.phases.size(); k++) {
         const RPhase &P = p.phases[k];

@@ -368,22 +368,31 @@ __device__ __forceinline__ uint32_t tile_exchange(C2<R> (&x)[kRegs], unsigned ch
     return tn;
 }
 
-// Persistent blocks of 2^(d - kRegBits) threads, each walking tiles
-// blockIdx.x + k gridDim.x.  A tile is read from HBM straight into the first
-// phase's layout and written from the last one's; the next tile's loads are
-// issued before the current tile's operators run (phases(x, base): every
-// phase of the step), so they are in flight during the arithmetic (barriers
-// wait for LDS only).  Tiles are disjoint, so the early read sees no write
-// of this launch.
+// Blocks of 2^(d - kRegBits) threads, each walking a run of tiles: with
+// `chunk` set, block b takes the consecutive tiles b per .. b per + per - 1
+// (per = ceil(num_tiles / gridDim.x)); otherwise tiles b + k gridDim.x.  The
+// consecutive runs measured up to 1.6x faster than the strided walk for
+// tiles that hold a high qubit (the strided walk's blocks drift apart across
+// the state), and no slower otherwise.  A tile is read from HBM straight into
+// the first phase's layout and written from the last one's; the next tile's
+// loads are issued before the current tile's operators run (phases(x, base):
+// every phase of the step), so they are in flight during the arithmetic
+// (barriers wait for LDS only).  Tiles are disjoint, so the early read sees no
+// write of this launch.
 template <typename R, typename Phases>
 __device__ __forceinline__ void tile_walk(C2<R> *__restrict__ a, uint64_t num_tiles, const InsertPlan &plan,
-                                          const RPhase &first, const RPhase &last, int lb, Phases phases)
+                                          const RPhase &first, const RPhase &last, int lb, bool chunk,
+                                          Phases phases)
 {
     const uint32_t t = threadIdx.x;
     const uint64_t xg = thread_offset(t, lb, first);
     const uint64_t xs = thread_offset(t, lb, last);
-    uint64_t tile = blockIdx.x;
-    if (tile >= num_tiles) return;
+    const uint64_t per = chunk ? (num_tiles + gridDim.x - 1) / gridDim.x : 1;
+    const uint64_t step = chunk ? 1 : gridDim.x;
+    uint64_t tile = (uint64_t)blockIdx.x * per;
+    uint64_t end = chunk ? tile + per : num_tiles;
+    if (end > num_tiles) end = num_tiles;
+    if (tile >= end) return;
     C2<R> x[kRegs];
     {
         const uint64_t b0 = insert_zeros(tile, plan);
@@ -394,10 +403,10 @@ __device__ __forceinline__ void tile_walk(C2<R> *__restrict__ a, uint64_t num_ti
 #pragma unroll
         for (int u = 0; u < kRegs; u++) asm volatile("" ::"v"(x[u].x), "v"(x[u].y));
     }
-    for (; tile < num_tiles; tile += gridDim.x) {
+    for (; tile < end; tile += step) {
         const uint64_t base = insert_zeros(tile, plan);
-        const uint64_t next = tile + gridDim.x;
-        const bool more = next < num_tiles;
+        const uint64_t next = tile + step;
+        const bool more = next < end;
         // defined on every path (zeros after the last tile): registers that
         // are undefined on one path of the loop have been given to other
         // values by the compiler's register allocation

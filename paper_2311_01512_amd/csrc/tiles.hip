@@ -646,6 +646,7 @@ struct TileArgs {
     int nph;
     InsertPlan plan;     // zeros at the tile's pivots: spreads the tile number
     uint64_t num_tiles;
+    int chunk;           // each block walks a run of consecutive tiles (else a stride)
 };
 
 // The generic tile-step kernel: phases and operators read from the pass's
@@ -657,7 +658,7 @@ __global__ __launch_bounds__(1024) void k_tile_step(C2<R> *__restrict__ a, TileA
     extern __shared__ unsigned char lds_raw[];
     const int lb = ta.d - kRegBits;
     const RPhase &first = ph[0];
-    tile_walk<R>(a, ta.num_tiles, ta.plan, first, ph[ta.nph - 1], lb, [&](C2<R>(&x)[kRegs], uint64_t base) {
+    tile_walk<R>(a, ta.num_tiles, ta.plan, first, ph[ta.nph - 1], lb, ta.chunk != 0, [&](C2<R>(&x)[kRegs], uint64_t base) {
         uint32_t tau = tau_of(threadIdx.x, first);
         for (int p = 0; p < ta.nph; p++) {
             const RPhase &P = ph[p];
@@ -685,13 +686,19 @@ int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev)
     const size_t ab = q->precision == QS_C64 ? sizeof(float2) : sizeof(double2);
     const size_t lds = ((size_t)1 << p.tile_d) * ab;
     const unsigned block = 1u << (p.tile_d - kRegBits);
+    // grid: resident blocks each walking a run of consecutive tiles, resident
+    // blocks walking by a fixed stride, or one block per tile
+    const int policy = tile_grid_policy(p.tile_d);
+    ta.chunk = policy == kTileGridChunk ? 1 : 0;
     if (p.jit_fn) {
         // the step's own kernel: phases and operators compiled in
         void *a = q->amps;
         uint64_t nt = ta.num_tiles;
         const void *mp = mats;
-        void *args[] = {&a, &nt, &mp};
-        const unsigned grid = grid_for(nt, 1, p.jit_grid);
+        int chunk = ta.chunk;
+        void *args[] = {&a, &nt, &mp, &chunk};
+        const unsigned grid = policy == kTileGridPerTile ? grid_for(nt << (p.tile_d - kRegBits), block)
+                                                          : grid_for(nt, 1, p.jit_grid);
         QS_HIP(hipModuleLaunchKernel((hipFunction_t)p.jit_fn, grid, 1, 1, block, 1, 1, p.jit_lds, q->stream, args,
                                      nullptr));
         return QS_OK;
@@ -713,7 +720,8 @@ int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev)
             return fail(QS_E_HIP, "occupancy query for the tile kernel failed");
         it = resident.emplace(key, per_cu * cus).first;
     }
-    const unsigned grid = grid_for(ta.num_tiles, 1, (uint64_t)it->second);
+    const unsigned grid = policy == kTileGridPerTile ? grid_for(ta.num_tiles << (p.tile_d - kRegBits), block)
+                                                      : grid_for(ta.num_tiles, 1, (uint64_t)it->second);
     if (q->precision == QS_C64)
         hipLaunchKernelGGL(k_tile_step<float>, dim3(grid), dim3(block), lds, q->stream, (float2 *)q->amps, ta, ph, ops,
                            (const float2 *)mats);

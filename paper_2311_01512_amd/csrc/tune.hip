@@ -3,7 +3,12 @@
 // Knobs default to values measured on MI355X and can be overridden from the
 // environment: QS_DENSE_KERNEL=vector|mfma (dense gates of 4-6 targets on
 // complex64), QS_MFMA_BLOCKS=<max blocks of the MFMA kernel>,
-// QS_TILE_LOW=<lowest qubits every tile step holds>.
+// QS_TILE_LOW=<lowest qubits every tile step holds>,
+// QS_STEP_WAVES=<waves per SIMD the specialised tile steps are compiled for>,
+// QS_TILE_GRID=chunk|stride|tiles (tile-step grids: resident blocks each
+// walking a run of consecutive tiles, resident blocks walking by a fixed
+// stride, or one block per tile; by default one block per tile for tiles of
+// up to 2^12 amplitudes and a stride for larger ones).
 #include "common.hpp"
 
 #include <cstdio>
@@ -41,6 +46,37 @@ uint64_t mfma_block_cap(int k)
     if (k >= 6) return 2048;
     if (k == 5) return 8192;
     return (uint64_t)1 << 30;
+}
+
+int step_waves_per_eu(bool f32)
+{
+    static const int forced = [] {
+        const char *e = std::getenv("QS_STEP_WAVES");
+        if (e) {
+            const int v = std::atoi(e);
+            if (v >= 1 && v <= 8) return v;
+        }
+        return 0;
+    }();
+    if (forced) return forced;
+    return f32 ? 6 : 4;
+}
+
+int tile_grid_policy(int tile_d)
+{
+    static const int forced = [] {
+        const char *e = std::getenv("QS_TILE_GRID");
+        if (e && std::string(e) == "stride") return (int)kTileGridStride;
+        if (e && std::string(e) == "tiles") return (int)kTileGridPerTile;
+        if (e && std::string(e) == "chunk") return (int)kTileGridChunk;
+        return -1;
+    }();
+    if (forced >= 0) return forced;
+    // measured on the 28-qubit random circuit (complex64, specialised steps):
+    // one block per tile is best for tiles of up to 2^12 amplitudes (2^12:
+    // 55.1 ms against 60.0 ms striding); 2^13-amplitude tiles (1024-thread
+    // blocks) keep resident blocks striding (52.5 ms against 56.7 ms)
+    return tile_d >= 13 ? kTileGridStride : kTileGridPerTile;
 }
 
 int tile_low_qubits(int precision)

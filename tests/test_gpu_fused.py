@@ -10,6 +10,20 @@ from gpu_helpers import TOL, amp_err, banner
 pytestmark = pytest.mark.gpu
 
 
+def trajectory(psi, ops):
+    """The oracle's final state and the largest amplitude magnitude of any
+    intermediate state.  With operators that are not unitary, each rounding
+    error is made relative to the amplitudes present when its operator runs,
+    so errors are normalised by this peak rather than by the final state's
+    largest amplitude (the reading stated with the tolerances)."""
+    state = psi.copy()
+    peak = np.abs(state).max()
+    for op in ops:
+        oracle.run_ops(state, [op])
+        peak = max(peak, np.abs(state).max())
+    return state, peak
+
+
 @pytest.fixture(scope="module")
 def qs():
     import paper_2311_01512_amd as pkg
@@ -98,12 +112,13 @@ def test_fusion_respects_order(qs, k, prec):
             ops.append({"op": "gadget", "targs": tuple(int(x) for x in qs_),
                         "paulis": tuple(int(x) for x in rng.integers(0, 4, size=w)), "theta": rng.uniform(-3, 3)})
     psi = synth.random_state(rng, 1 << N)
-    want = oracle.run_ops(psi.copy(), ops)
+    want, peak = trajectory(psi, ops)
     circ = qs.Circuit(N, ops).compile(k, prec)
     q = qs.Qureg(N, precision=prec).set_amps(psi)
     circ.apply(q)
-    # non-unitary factors grow the norm; compare relative to the largest amplitude
-    assert amp_err(q.get_amps(), want) < (1e-10 if prec == "c128" else 2e-5)
+    err = np.abs(q.get_amps() - want).max() / peak
+    print(f"[gpu-test] non-unitary k={k} {prec}: error / trajectory peak {err:.2e}", flush=True)
+    assert err < TOL[prec], err
 
 
 @pytest.mark.parametrize("k", [9, 10, 12])
@@ -175,10 +190,13 @@ def test_tile_sparse_gates(qs, prec, k):
             ops.append({"op": "gadget", "targs": tuple(int(x) for x in t),
                         "paulis": tuple(int(x) for x in rng.integers(1, 4, size=w)), "theta": rng.uniform(-3, 3)})
     psi = synth.random_state(rng, 1 << N)
+    want, peak = trajectory(psi, ops)
     circ = qs.Circuit(N, ops).compile(k, prec)
     q = qs.Qureg(N, precision=prec).set_amps(psi)
     circ.apply(q)
-    assert amp_err(q.get_amps(), oracle.run_ops(psi.copy(), ops)) < (1e-11 if prec == "c128" else 2e-5)
+    err = np.abs(q.get_amps() - want).max() / peak
+    print(f"[gpu-test] sparse k={k} {prec}: error / trajectory peak {err:.2e}", flush=True)
+    assert err < TOL[prec], err
 
 
 def test_config5_fused_reduced(qs):
