@@ -417,6 +417,34 @@ int qs_circuit_autotune_ex(qs_qureg *q, qs_circuit *c, const int *candidates, in
                            int try_specialized, int *best_k, int *best_specialized, double *ms_out,
                            double *ms_specialized_out);
 
+/* ---- adjoint gradients of a statevector circuit --------------------------------- */
+
+/*
+ * Parametrised Pauli gadget exp(i * scale * params[param] * P) (Sec. "Pauli
+ * gadget"; P a Pauli string on distinct qubits, codes 0..3) appended to a
+ * statevector circuit; its angle is set by qs_circuit_set_params (0 until
+ * then).  Density circuits: QS_E_PRECOND.
+ */
+int qs_circuit_add_param_gadget(qs_circuit *c, const int *targs, const int *paulis, int num_targs, int param,
+                                double scale);
+/* Sets every parametrised gadget's angle to scale * params[param].  The
+ * circuit must be compiled again before qs_apply_circuit. */
+int qs_circuit_set_params(qs_circuit *c, const double *params, int num_params);
+/*
+ * Energy E = <psi|H|psi> of H = sum_n coeffs[n] P_n (paulis: num_terms
+ * strings of N codes, term-major) after the circuit, and dE/dparams[p] for
+ * every parameter, by the adjoint method: psi (holding the initial state)
+ * is run through the circuit one operator per pass, lambda = H psi (lam: a
+ * statevector qureg of the same size, precision and stream, overwritten),
+ * then for each operator from last to first dE/dtheta_p += -2 scale
+ * Im <lambda|P|psi> for a parametrised gadget and psi, lambda <-
+ * U^dag psi, U^dag lambda.  On return psi holds the initial state again (up
+ * to rounding).  grads receives num_params values; energy one.  Sums in FP64.
+ */
+int qs_circuit_adjoint_gradient(qs_circuit *c, qs_qureg *psi, qs_qureg *lam, const int *paulis,
+                                const double *coeffs, int num_terms, int num_params, double *energy,
+                                double *grads);
+
 /* ---- batches: many parametrised circuits of uneven size, with energies and
  *      adjoint gradients ------------------------------------------------------ */
 
@@ -450,6 +478,16 @@ int qs_batch_add_circuit(qs_batch *b, int num_qubits, int num_params, int *index
 /* exp(i * scale * params[param] * P) on `qubit`, pauli 1 = X, 2 = Y, 3 = Z.
  * RY(a) = exp(-i a Y / 2) is pauli 2 with scale -0.5. */
 int qs_batch_add_rotation(qs_batch *b, int circuit, int qubit, int pauli, int param, double scale);
+/* The Pauli gadget exp(i * scale * params[param] * P) (Sec. "Pauli gadget")
+ * of a Pauli string on num_targs distinct qubits (codes 0..3; identities
+ * ignored, at least one non-identity), or with param = -1 the fixed gadget
+ * exp(i * scale * P).  It is recorded as the rotation exp(i theta X) on one of
+ * its qubits between parameter-free Clifford gates (basis changes and CZs
+ * that map that rotation onto the gadget), so the adjoint sweep's gradient
+ * with respect to the parameter is the gadget's.  Counts as one operator in
+ * qs_batch_stats. */
+int qs_batch_add_gadget(qs_batch *b, int circuit, const int *targs, const int *paulis, int num_targs,
+                        int param, double scale);
 /* A fixed 2 x 2 gate (row-major (re, im) doubles) on `qubit`. */
 int qs_batch_add_gate1(qs_batch *b, int circuit, int qubit, const double *matrix);
 /* Controlled-Z on two distinct qubits (diagonal, symmetric). */

@@ -22,4 +22,7 @@ def __getattr__(name):
     if name in ("BatchEnergy", "energies"):
         from . import batch
         return getattr(batch, name)
+    if name in ("CircuitEnergy", "circuit_energy"):
+        from . import circuit
+        return getattr(circuit, name)
     raise AttributeError(name)

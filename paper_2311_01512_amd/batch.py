@@ -17,22 +17,27 @@ class Batch:
         self.compiled = False
 
     def add_circuit(self, num_qubits, ops, num_params, codes=None, coeffs=None):
-        """ops: op dicts; supported are single-qubit gadgets carrying a
-        parameter ({"op": "gadget", "targs": (q,), "paulis": (p,), "param": k,
-        "scale": s}: exp(i s theta_k P)), fixed single-qubit unitaries, and
-        CZ (a Z unitary with one control)."""
+        """ops: op dicts; supported are Pauli gadgets carrying a parameter
+        ({"op": "gadget", "targs": (...), "paulis": (...), "param": k,
+        "scale": s}: exp(i s theta_k P), any weight), fixed Pauli gadgets
+        ({"op": "gadget", ..., "theta": t} without "param"), fixed
+        single-qubit unitaries, and CZ (a Z unitary with one control)."""
         c = N.qs_batch_add_circuit(self._b, num_qubits, num_params)
         for op in ops:
-            if op["op"] == "gadget" and "param" in op and len(op["targs"]) == 1:
+            if op["op"] == "gadget" and "param" in op and len(op["targs"]) == 1 and op["paulis"][0] != 0:
                 N.qs_batch_add_rotation(self._b, c, op["targs"][0], op["paulis"][0], op["param"],
                                         op.get("scale", 1.0))
+            elif op["op"] == "gadget" and "param" in op:
+                N.qs_batch_add_gadget(self._b, c, op["targs"], op["paulis"], op["param"], op.get("scale", 1.0))
+            elif op["op"] == "gadget":
+                N.qs_batch_add_gadget(self._b, c, op["targs"], op["paulis"], -1, op["theta"])
             elif op["op"] == "unitary" and not op["ctrls"] and len(op["targs"]) == 1:
                 N.qs_batch_add_gate1(self._b, c, op["targs"][0], op["matrix"])
             elif (op["op"] == "unitary" and len(op["ctrls"]) == 1 and len(op["targs"]) == 1
                   and np.allclose(op["matrix"], np.diag([1, -1]))):
                 N.qs_batch_add_cz(self._b, c, op["ctrls"][0], op["targs"][0])
             else:
-                raise ValueError("batches hold parametrised single-qubit rotations, single-qubit gates and CZ")
+                raise ValueError("batches hold Pauli gadgets (parametrised or fixed), single-qubit gates and CZ")
         if codes is not None:
             N.qs_batch_set_observable(self._b, c, codes, coeffs, num_qubits)
         self.num_qubits.append(num_qubits)

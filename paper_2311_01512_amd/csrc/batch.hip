@@ -24,6 +24,7 @@ struct BOp {
     int kind, q0, q1, pauli, param;
     double scale;
     cd m[4];
+    int logical = 1;  // operators of the recorded circuit it stands for (0: part of a decomposed gadget)
     uint64_t support() const { return (1ULL << q0) | (kind == BOP_CZ ? (1ULL << q1) : 0ULL); }
 };
 
@@ -1126,6 +1127,109 @@ int qs_batch_add_gate1(qs_batch *b, int circuit, int qubit, const double *m)
     return QS_OK;
 }
 
+// A Pauli gadget exp(i theta P) on several qubits (Sec. "Pauli gadget") as
+// the rotation exp(i theta X_w) on one of its qubits w between Clifford
+// gates: exp(i theta P) = B^dag exp(i theta Z_S) B with B the per-qubit basis
+// change (H for X, H S^dag for Y) that turns P into Z_S on its support S, and
+// exp(i theta Z_S) = L exp(i theta Z_w) L with L the CNOTs from every other
+// qubit of S onto w (L Z_w L = Z_S); CNOT(c, w) = H_w CZ(c, w) H_w and
+// H_w exp(i theta Z_w) H_w = exp(i theta X_w).  In circuit order: H_w B_w on
+// w and B_q on the others, the CZs, the rotation, the CZs, B^dag and H_w.
+// The Clifford gates do not depend on theta, so the adjoint sweep's
+// derivative of the rotation is the gadget's.
+static int add_gadget(qs_batch *b, BCirc *c, const int *targs, const int *paulis, int n, int param, double scale)
+{
+    std::vector<int> q, pc;
+    for (int k = 0; k < n; k++) {
+        if (targs[k] < 0 || targs[k] >= c->n) return fail(QS_E_ARG, "qubit out of range");
+        if (paulis[k] < 0 || paulis[k] > 3) return fail(QS_E_ARG, "Pauli codes are 0..3");
+        for (int j = 0; j < k; j++)
+            if (targs[j] == targs[k]) return fail(QS_E_ARG, "duplicate qubit");
+        if (paulis[k]) {
+            q.push_back(targs[k]);
+            pc.push_back(paulis[k]);
+        }
+    }
+    if (q.empty()) return fail(QS_E_ARG, "an identity string is a global phase, not a gadget");
+    if (param >= c->num_params) return fail(QS_E_ARG, "parameter index out of range");
+    const double r = 1.0 / std::sqrt(2.0);
+    const cd I(0, 1);
+    const cd H[4] = {r, r, r, -r};
+    const cd BY[4] = {r, -I * r, r, I * r};          // H S^dag
+    const cd BYd[4] = {r, r, I * r, -I * r};         // (H S^dag)^dag
+    const cd SD[4] = {1, 0, 0, -I};                  // S^dag
+    const cd S[4] = {1, 0, 0, I};
+    auto gate = [&](int qubit, const cd *m) {
+        BOp op{};
+        op.kind = BOP_GATE;
+        op.q0 = op.q1 = qubit;
+        for (int k = 0; k < 4; k++) op.m[k] = m[k];
+        op.logical = 0;
+        c->ops.push_back(op);
+    };
+    auto cz = [&](int a, int w) {
+        BOp op{};
+        op.kind = BOP_CZ;
+        op.q0 = a;
+        op.q1 = w;
+        op.logical = 0;
+        c->ops.push_back(op);
+    };
+    const size_t wi = q.size() - 1;   // the rotation's qubit
+    const int w = q[wi];
+    // basis changes (pivot: H_w B_w = I for X, S^dag for Y, H for Z)
+    for (size_t k = 0; k < q.size(); k++) {
+        if (k == wi) {
+            if (pc[k] == 2) gate(w, SD);
+            else if (pc[k] == 3) gate(w, H);
+        } else if (pc[k] == 1) {
+            gate(q[k], H);
+        } else if (pc[k] == 2) {
+            gate(q[k], BY);
+        }
+    }
+    for (size_t k = 0; k < wi; k++) cz(q[k], w);
+    BOp rot{};
+    if (param >= 0) {
+        rot.kind = BOP_ROT;
+        rot.pauli = 1;
+        rot.param = param;
+        rot.scale = scale;
+    } else {
+        // fixed angle: exp(i scale X) as a gate
+        rot.kind = BOP_GATE;
+        const double co = std::cos(scale), si = std::sin(scale);
+        rot.m[0] = co;
+        rot.m[1] = I * si;
+        rot.m[2] = I * si;
+        rot.m[3] = co;
+    }
+    rot.q0 = rot.q1 = w;
+    c->ops.push_back(rot);
+    for (size_t k = 0; k < wi; k++) cz(q[k], w);
+    for (size_t k = 0; k < q.size(); k++) {
+        if (k == wi) {
+            if (pc[k] == 2) gate(w, S);
+            else if (pc[k] == 3) gate(w, H);
+        } else if (pc[k] == 1) {
+            gate(q[k], H);
+        } else if (pc[k] == 2) {
+            gate(q[k], BYd);
+        }
+    }
+    b->compiled = false;
+    return QS_OK;
+}
+
+int qs_batch_add_gadget(qs_batch *b, int circuit, const int *targs, const int *paulis, int num_targs, int param,
+                        double scale)
+{
+    BCirc *c = circ_at(b, circuit);
+    if (!c) return fail(QS_E_ARG, "no such circuit");
+    if (num_targs < 1 || !targs || !paulis) return fail(QS_E_ARG, "empty Pauli string");
+    return add_gadget(b, c, targs, paulis, num_targs, param, scale);
+}
+
 int qs_batch_add_cz(qs_batch *b, int circuit, int q1, int q2)
 {
     BCirc *c = circ_at(b, circuit);
@@ -1475,7 +1579,9 @@ int qs_batch_stats(const qs_batch *b, int *num_circuits, int *num_steps, uint64_
     uint64_t amps = 0, upd = 0;
     for (const auto &c : b->circs) {
         amps += 1ULL << c.n;
-        upd += (uint64_t)c.ops.size() << c.n;
+        uint64_t n_ops = 0;
+        for (const auto &op : c.ops) n_ops += (uint64_t)op.logical;
+        upd += n_ops << c.n;
     }
     if (total_amps) *total_amps = amps;
     if (logical_updates) *logical_updates = upd;

@@ -12,6 +12,8 @@ struct CircOp {
     std::vector<cd> M;                // unitary matrix, row-major 2^nt x 2^nt
     std::vector<int> paulis;          // gadget: codes per target
     double theta;
+    int param = -1;                   // parametrised gadget: theta = scale * params[param]
+    double scale = 1.0;
     std::vector<int> support() const
     {
         std::vector<int> s;

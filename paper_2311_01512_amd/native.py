@@ -95,6 +95,10 @@ _SIGS = {
     "qs_batch_add_rotation": [_P, _I, _I, _I, _I, _D],
     "qs_batch_add_gate1": [_P, _I, _I, _P],
     "qs_batch_add_cz": [_P, _I, _I, _I],
+    "qs_circuit_add_param_gadget": [_P, _P, _P, _I, _I, _D],
+    "qs_circuit_set_params": [_P, _P, _I],
+    "qs_circuit_adjoint_gradient": [_P, _P, _P, _P, _P, _I, _I, _PD, _P],
+    "qs_batch_add_gadget": [_P, _I, _P, _P, _I, _I, _D],
     "qs_batch_set_observable": [_P, _I, _P, _P, _I],
     "qs_batch_compile": [_P, _P, _I],
     "qs_batch_run": [_P, _P, _P, _P],
@@ -458,6 +462,37 @@ def qs_batch_add_gate1(b, circuit, qubit, matrix):
     _square(matrix, 2, "matrix")
     m = cmatrix(matrix)
     check(lib.qs_batch_add_gate1(b, circuit, qubit, ptr(m)), "qs_batch_add_gate1")
+
+
+def qs_batch_add_gadget(b, circuit, targs, paulis, param, scale):
+    t, p = ints(targs), ints(paulis)
+    if t.size != p.size:
+        raise ValueError("one Pauli code per target")
+    check(lib.qs_batch_add_gadget(b, circuit, ptr(t), ptr(p), t.size, param, scale), "qs_batch_add_gadget")
+
+
+def qs_circuit_add_param_gadget(c, targs, paulis, param, scale):
+    t, p = ints(targs), ints(paulis)
+    if t.size != p.size:
+        raise ValueError("one Pauli code per target")
+    check(lib.qs_circuit_add_param_gadget(c, ptr(t), ptr(p), t.size, param, scale), "qs_circuit_add_param_gadget")
+
+
+def qs_circuit_set_params(c, params):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    check(lib.qs_circuit_set_params(c, ptr(p), p.size), "qs_circuit_set_params")
+
+
+def qs_circuit_adjoint_gradient(c, psi, lam, paulis, coeffs, num_qubits, num_params):
+    p = np.ascontiguousarray(np.asarray(paulis, dtype=np.int32))
+    h = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+    if p.size != h.size * num_qubits:
+        raise ValueError("need num_terms * num_qubits Pauli codes")
+    e = C.c_double()
+    g = np.zeros(num_params, dtype=np.float64)
+    check(lib.qs_circuit_adjoint_gradient(c, psi, lam, ptr(p), ptr(h), h.size, num_params, C.byref(e), ptr(g)),
+          "qs_circuit_adjoint_gradient")
+    return e.value, g
 
 
 def qs_batch_add_cz(b, circuit, q1, q2):
