@@ -2,17 +2,23 @@
 
 A step is one application of the 500-gate circuit (Haar 1-qubit gates,
 2-target Haar gates with 0-3 controls, Pauli gadgets exp(i theta P) of weight
-1-28) to a 2^28-amplitude statevector resident in HBM.  Two paths are timed:
+1-28) to a 2^28-amplitude statevector resident in HBM.  Paths timed:
 
-* fused: complex64 state, gates fused into dense k-qubit blocks (FP64
-  products), blocks of 4-6 qubits run as FP32 MFMA GEMMs; k is picked by the
-  library's autotuner.  This is the headline `value`.
-* plain: complex128 state, one pass per gate (the paper's per-gate method).
+* fused complex64: the library's autotuner picks plain passes, dense
+  k-qubit blocks (FP32 MFMA for 4-6 qubits) or tile steps (many operators
+  per HBM pass), generic or compiled per step.  This is the headline
+  `value`.
+* plain complex128: one pass per gate (the paper's per-gate method).
+* fused complex128: the autotuned complex128 tile steps.
 
 `value` is logical amplitude-updates/s (plain per-gate accounting: 2^(N-s)
-per s-controlled gate, 2^N per gadget, credited alike to both paths).  The
-fused complex64 state is compared amplitude by amplitude with the complex128
-one after the same number of circuit applications from the same state.
+per s-controlled gate, 2^N per gadget, credited alike to every path).  The
+timed region is `--steps` applications with every pass bracketed by HIP
+events on the qureg's stream; the roofline's per-launch average comes from
+those events.  Each path's state after one application from the
+counter-hashed state is compared with the oracle's (the CPU baseline run,
+the whole circuit on the host cores).  The default line also carries the
+14-qubit density-matrix workload and the 512-circuit batch as sub-objects.
 
 Prints one JSON line.
 """
@@ -27,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
 
 
 def parse():
@@ -38,8 +45,12 @@ def parse():
     ap.add_argument("--gates", type=int, default=500)
     ap.add_argument("--fuse-candidates", default="0,4,5,10,11,12,13",
                     help="fusion widths the autotuner tries: 0 plain, 2-6 dense blocks, 8-14 LDS tiles")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-runs", type=int, default=1,
+                    help="runs of the oracle over the whole circuit for the CPU baseline (median taken)")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle (CPU baseline and the error against the oracle)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="headline only: skip the density-matrix and batched sub-lines")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for hardware-counter collection: one torch copy of 2 GiB "
                          "(the calibration kernel of known traffic), then one application of the "
@@ -107,33 +118,58 @@ def time_steps(circ, q, steps, torch):
     return a.elapsed_time(b) * 1e-3 / steps
 
 
-def time_passes(circ, q, torch):
-    """One application pass by pass, each bracketed by HIP events; returns
-    kernel -> [launches, total ms, amplitudes touched, flops]."""
+def pass_kinds(circ, q):
+    """Per pass of a compiled circuit: (kernel name, amplitudes it reads and
+    writes once, flops)."""
     n = 2 * q.num_qubits if q.density else q.num_qubits     # index bits
     real = "float" if q.precision == "c64" else "double"
-    npass = circ.stats()["num_passes"]
-    infos = [circ.pass_info(i) for i in range(npass)]
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in infos]
-    torch.cuda.synchronize()
-    for i, (a, b) in enumerate(ev):
-        a.record(q.stream)
-        circ.apply_passes(q, i, 1)
-        b.record(q.stream)
-    torch.cuda.synchronize()
-    out = {}
-    for info, (a, b) in zip(infos, ev):
+    out = []
+    for i in range(circ.stats()["num_passes"]):
+        info = circ.pass_info(i)
         name = kernel_name(info, real, circ.specialized > 0)
         amps = 1 << (n - info["num_ctrls"])
         if info["kernel"] == "tile":
             amps = 1 << n          # one read and one write of the whole state per step
         flops = 8 * (1 << info["num_targs"]) * amps if info["kernel"].startswith("dense") else 0
-        c = out.setdefault(name, [0, 0.0, 0, 0])
-        c[0] += 1
-        c[1] += a.elapsed_time(b)
-        c[2] += amps
-        c[3] += flops
+        out.append((name, amps, flops))
     return out
+
+
+def timed_region(circ, q, steps, torch):
+    """The timed region: `steps` applications of the circuit, each pass
+    bracketed by HIP events on the qureg's stream (the stream the kernels
+    are launched on).  Returns (seconds per application over the whole
+    region, kernel -> [launches, total ms, amplitudes, flops] summed over
+    every pass of every application)."""
+    kinds = pass_kinds(circ, q)
+    npass = len(kinds)
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(npass)]
+          for _ in range(steps)]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(q.stream)
+    for s_ in range(steps):
+        for i in range(npass):
+            ev[s_][i][0].record(q.stream)
+            circ.apply_passes(q, i, 1)
+            ev[s_][i][1].record(q.stream)
+    b.record(q.stream)
+    b.synchronize()
+    out = {}
+    for s_ in range(steps):
+        for (name, amps, flops), (e0, e1) in zip(kinds, ev[s_]):
+            c = out.setdefault(name, [0, 0.0, 0, 0])
+            c[0] += 1
+            c[1] += e0.elapsed_time(e1)
+            c[2] += amps
+            c[3] += flops
+    return a.elapsed_time(b) * 1e-3 / steps, out
+
+
+def time_passes(circ, q, torch):
+    """One application pass by pass, each bracketed by HIP events; returns
+    kernel -> [launches, total ms, amplitudes touched, flops]."""
+    return timed_region(circ, q, 1, torch)[1]
 
 
 def per_kernel_table(kinds, amp_bytes):
@@ -157,41 +193,60 @@ def roofline(kinds, amp_bytes, workload):
             "kernel": name, "avg_launch_ms": avg_s * 1e3, "bytes_per_launch": bytes_per_launch}
 
 
-def cpu_baseline(ops, n, budget_s):
+def host_cpu():
+    """Host CPU as the oracle sees it: usable cores and the model name."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"nproc": usable, "cpu_count": os.cpu_count(), "model": model}
+
+
+def cpu_baseline(ops, n, seed, runs):
+    """The oracle (plain per-gate complex128 on the host cores, OpenMP) on
+    the whole circuit from the counter-hashed state the GPU paths start
+    from; the median of `runs` runs.  Returns (baseline record, the oracle's
+    final state)."""
+    import statistics
     import oracle
-    psi = oracle.hashed_state(n, 7)
-    t0 = time.perf_counter()
-    done, updates = 0, 0
+    updates = 0
     for op in ops:
-        oracle.run_ops(psi, [op])
-        done += 1
         updates += (1 << n) if op["op"] == "gadget" else (1 << (n - len(op["ctrls"])))
-        if time.perf_counter() - t0 > budget_s and done >= 2:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": updates / dt, "unit": "amplitude-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"first {done} of {len(ops)} gates of the {n}-qubit circuit, plain per-gate "
-                      f"complex128, {dt:.1f} s"}
+    times = []
+    psi = None
+    for _ in range(runs):
+        psi = oracle.hashed_state(n, seed)
+        t0 = time.perf_counter()
+        oracle.run_ops(psi, ops)
+        times.append(time.perf_counter() - t0)
+    dt = statistics.median(times)
+    cpu = host_cpu()
+    rec = {"value": updates / dt, "unit": "amplitude-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"the whole {len(ops)}-gate {n}-qubit circuit, plain per-gate complex128, from the "
+                     f"counter-hashed state (seed {seed}); median of {runs} run(s): "
+                     + ", ".join(f"{t:.1f} s" for t in times),
+           "nproc": cpu["nproc"], "cpu_model": cpu["model"], "seconds": times}
+    return rec, psi
 
 
-def copy_ceiling(torch, reps=5):
-    """A plain 2 GiB device copy (torch's copy kernel, 2 GiB read + 2 GiB
-    written per copy): the HBM rate a streaming kernel can reach in
-    practice on this GPU, for reading the roofline fraction against."""
-    src = torch.zeros(1 << 28, dtype=torch.complex64, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    b.record()
-    b.synchronize()
-    gbps = 2 * src.numel() * 8 * reps / (a.elapsed_time(b) * 1e-3) / 1e9
-    del src, dst
-    torch.cuda.empty_cache()
-    return gbps
+def streaming_ceiling(qs, q, torch, reps=5):
+    """The fastest in-house streaming kernel on this state: a Pauli-X gadget
+    on the highest qubit (k_gadget_pairs: each thread reads and writes a
+    pair of amplitudes half the state apart, in runs of consecutive
+    addresses), as the HBM rate a kernel of this library reaches when it
+    only streams."""
+    n = q.num_qubits
+    c = qs.Circuit(n, [{"op": "gadget", "targs": (n - 1,), "paulis": (1,), "theta": 0.3}]).compile(0, q.precision)
+    c.apply(q)
+    ms = time_steps(c, q, reps, torch) * 1e3
+    ab = 8 if q.precision == "c64" else 16
+    return {"kernel": f"k_gadget_pairs<{'float' if ab == 8 else 'double'}> (X gadget on qubit {n - 1})",
+            "ms": ms, "GBps": 2 * ab * q.num_amps / (ms * 1e-3) / 1e9}
 
 
 def pmc_probe(args):
@@ -422,10 +477,14 @@ def bench_density(args, torch, qs, synth):
     circ.apply(q)
     with torch.no_grad():
         err = ((q.tensor.to(torch.complex128) - ref).abs().max() / ref.abs().max()).item()
+    # the partial trace into a preallocated output: kernel time only
+    red = q.partial_trace(traced)
+    q.sync()
     ta = torch.cuda.Event(enable_timing=True)
     tb = torch.cuda.Event(enable_timing=True)
     ta.record(q.stream)
-    red = q.partial_trace(traced)
+    for _ in range(10):
+        q.partial_trace(traced, out=red)
     tb.record(q.stream)
     tb.synchronize()
     tr, pur = q.trace(), q.purity()
@@ -435,7 +494,7 @@ def bench_density(args, torch, qs, synth):
              "autotune_specialised_ms": spec_ms and {str(k): v for k, v in spec_ms.items()},
              "specialised_kernels": circ.specialized,
              "passes": st["num_passes"], "max_amp_err_vs_c128": err, "per_kernel": per_kernel_table(kinds, 8),
-             "partial_trace_ms": ta.elapsed_time(tb),
+             "partial_trace_ms": ta.elapsed_time(tb) / 10,
              "trace": [tr.real, tr.imag], "purity": [pur.real, pur.imag],
              "reduced_trace": red.trace().real, "reduced_purity": red.purity().real}
     line = base_line(fused["value"], "amplitude-updates/s", args.steps, args.warmup, fused["ms_per_step"],
@@ -473,10 +532,26 @@ def bench_batch(args, torch, qs, synth):
     fwd = (time.perf_counter() - t0) / args.steps
     fwd_upd = st["logical_updates"]
     total = 3 * fwd_upd      # forward, then U^dagger on phi and on lambda
+    # algorithmic FP32 flops of one run: a single-qubit operator is a 2 x 2
+    # complex matrix on every amplitude (14 flops per amplitude: two complex
+    # products and a sum), CZ none; the adjoint sweep applies each operator
+    # to two states and forms conj(lambda) P phi (8 flops per amplitude) for
+    # every rotation; lambda = H psi costs 8 flops per amplitude and term
+    flops = 0
+    for p in probs:
+        a = 1 << p["num_qubits"]
+        one_q = sum(1 for op in p["ops"] if op["op"] == "gadget" or not op.get("ctrls"))
+        rot = sum(1 for op in p["ops"] if op["op"] == "gadget" and "param" in op)
+        flops += a * (14 * one_q + 2 * 14 * one_q + 8 * rot + 8 * len(p["coeffs"]))
+    achieved = flops / full / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "kernel": "batch replay (forward, energies, adjoint sweep; states stay in LDS / L2)",
+            "flops_per_run": flops}
     return base_line(total / full, "amplitude-updates/s", args.steps, args.warmup, full * 1e3, "c64 (f32)",
                      "512 statevectors, N ~ U{10..22}, 6-layer hardware-efficient ansatz, 20-term Pauli-sum "
                      "energy and adjoint gradient over all angles, one HIP-graph replay",
-                     {"circuits": st["num_circuits"], "total_amplitudes": st["total_amps"],
+                     {"roofline": roof, "circuits": st["num_circuits"], "total_amplitudes": st["total_amps"],
                       "launch_steps": st["num_steps"], "forward_only_ms": fwd * 1e3,
                       "forward_updates_per_s": fwd_upd / fwd, "gradients": int(params.size),
                       "circuits_per_s_with_gradient": st["num_circuits"] / full,
@@ -564,19 +639,24 @@ def main():
     plain = qs.Circuit(n, ops).compile(0, "c128")
     q128 = qs.Qureg(n, precision="c128")
 
+    # one application of each path from the counter-hashed state: kept for
+    # the comparison with the oracle's result
     q64.init_hashed(seed)
     q128.init_hashed(seed)
+    fused.apply(q64)
+    plain.apply(q128)
+    torch.cuda.synchronize()
+    saved = {"fused_c64": q64.tensor.clone(), "plain_c128": q128.tensor.clone()}
+    with torch.no_grad():
+        ref = saved["plain_c128"]
+        err = ((saved["fused_c64"].to(torch.complex128) - ref).abs().max() / ref.abs().max()).item()
+
     for _ in range(args.warmup):
         fused.apply(q64)
         plain.apply(q128)
-    t64 = time_steps(fused, q64, args.steps, torch)
-    t128 = time_steps(plain, q128, args.steps, torch)
-    kinds64 = time_passes(fused, q64, torch)
-    kinds128 = time_passes(plain, q128, torch)
-
-    with torch.no_grad():
-        ref = q128.tensor
-        err = ((q64.tensor.to(torch.complex128) - ref).abs().max() / ref.abs().max()).item()
+    t64, kinds64 = timed_region(fused, q64, args.steps, torch)
+    t128, kinds128 = timed_region(plain, q128, args.steps, torch)
+    t64_plain_launch = time_steps(fused, q64, args.steps, torch)
 
     st = fused.stats()
     result = {
@@ -597,7 +677,8 @@ def main():
                    "num_qubits": n, "gates": len(ops),
                    "path": f"complex64, {path_text(best_k, fused.specialized > 0)} (fusion width autotuned)"},
         "roofline": roofline(kinds64, 8, workload),
-        "fused_c64": {"value": logical / t64, "ms_per_step": t64 * 1e3, "fuse_k": best_k,
+        "fused_c64": {"value": logical / t64, "ms_per_step": t64 * 1e3,
+                      "ms_per_step_without_pass_events": t64_plain_launch * 1e3, "fuse_k": best_k,
                       "autotune_ms": {str(k): v for k, v in tune_ms.items()},
                       "autotune_specialised_ms": spec_ms and {str(k): v for k, v in spec_ms.items()},
                       "specialised_kernels": fused.specialized,
@@ -611,12 +692,51 @@ def main():
         "reductions_c128": bench_reductions(q128, torch, 16),
         "reductions_c64": bench_reductions(q64, torch, 8),
     }
-    copy_gbps = copy_ceiling(torch)
-    result["hbm_copy_ceiling"] = {"GBps": copy_gbps, "frac_of_peak": copy_gbps / 8000.0,
-                                  "roofline_achieved_over_copy": (result["roofline"]["achieved"] / copy_gbps
-                                                                  if result["roofline"]["unit"] == "GB/s" else None)}
+    # fused complex128: tile steps at the widest complex128 tile, specialised
+    del q128
+    torch.cuda.empty_cache()
+    f128 = qs.Circuit(n, ops)
+    qf128 = qs.Qureg(n, precision="c128")
+    k128, tune128, spec128 = autotune(f128, qf128, (0, 9, 10, 11), args)
+    qf128.init_hashed(seed)
+    f128.apply(qf128)
+    torch.cuda.synchronize()
+    saved["fused_c128"] = qf128.tensor.clone()
+    for _ in range(args.warmup):
+        f128.apply(qf128)
+    tf128, kindsf128 = timed_region(f128, qf128, args.steps, torch)
+    result["fused_c128"] = {"value": logical / tf128, "ms_per_step": tf128 * 1e3, "fuse_k": k128,
+                            "path": "complex128, " + path_text(k128, f128.specialized > 0),
+                            "autotune_ms": {str(k): v for k, v in tune128.items()},
+                            "autotune_specialised_ms": spec128 and {str(k): v for k, v in spec128.items()},
+                            "passes": f128.stats()["num_passes"], "roofline": roofline(kindsf128, 16, workload),
+                            "speedup_vs_plain_c128": t128 / tf128}
+    del qf128, f128
+    torch.cuda.empty_cache()
+    # the fastest in-house streaming kernel, for reading the roofline fraction
+    stream = streaming_ceiling(qs, q64, torch)
+    stream["frac_of_peak"] = stream["GBps"] / HBM_PEAK_GBS
+    if result["roofline"]["unit"] == "GB/s":
+        stream["roofline_achieved_over_streaming"] = result["roofline"]["achieved"] / stream["GBps"]
+    result["streaming_ceiling"] = stream
+    del q64
+    torch.cuda.empty_cache()
+    if not args.no_workloads:
+        result["density14"] = bench_density(args, torch, qs, synth)
+        result["batch512"] = bench_batch(args, torch, qs, synth)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_seconds)
+        base, psi = cpu_baseline(ops, n, seed, args.cpu_runs)
+        result["cpu_baseline"] = base
+        want = torch.from_numpy(psi).to("cuda")
+        del psi
+        with torch.no_grad():
+            scale = want.abs().max()
+            errs = {k: ((v.to(torch.complex128) - want).abs().max() / scale).item() for k, v in saved.items()}
+        result["max_amp_err_vs_oracle"] = errs
+        result["fused_c64"]["max_amp_err_vs_oracle"] = errs["fused_c64"]
+        result["plain_c128"]["max_amp_err_vs_oracle"] = errs["plain_c128"]
+        result["fused_c128"]["max_amp_err_vs_oracle"] = errs["fused_c128"]
+        del want
     print(json.dumps(result), flush=True)
 
 
