@@ -135,7 +135,20 @@ def pass_kinds(circ, q):
     return out
 
 
-def timed_region(circ, q, steps, torch):
+def line_amps(ops, n, amp_bytes):
+    """Per operator of a plain (one pass per operator) circuit: amplitudes of
+    the 128-byte lines its kernel must read and write.  A control on a qubit
+    inside a line (the 3 (complex128) or 4 (complex64) lowest) selects half
+    of every line, so it does not shrink the set of lines touched."""
+    low = 3 if amp_bytes == 16 else 4
+    out = []
+    for op in ops:
+        hi = [c for c in op.get("ctrls", ()) if c >= low] if op["op"] == "unitary" else []
+        out.append(1 << (n - len(hi)))
+    return out
+
+
+def timed_region(circ, q, steps, torch, lines=None):
     """The timed region: `steps` applications of the circuit, each pass
     bracketed by HIP events on the qureg's stream (the stream the kernels
     are launched on).  Returns (seconds per application over the whole
@@ -157,12 +170,13 @@ def timed_region(circ, q, steps, torch):
     b.synchronize()
     out = {}
     for s_ in range(steps):
-        for (name, amps, flops), (e0, e1) in zip(kinds, ev[s_]):
-            c = out.setdefault(name, [0, 0.0, 0, 0])
+        for i, ((name, amps, flops), (e0, e1)) in enumerate(zip(kinds, ev[s_])):
+            c = out.setdefault(name, [0, 0.0, 0, 0, 0])
             c[0] += 1
             c[1] += e0.elapsed_time(e1)
             c[2] += amps
             c[3] += flops
+            c[4] += lines[i] if lines else amps
     return a.elapsed_time(b) * 1e-3 / steps, out
 
 
@@ -173,13 +187,23 @@ def time_passes(circ, q, torch):
 
 
 def per_kernel_table(kinds, amp_bytes):
-    return {k: {"launches": v[0], "avg_ms": v[1] / v[0],
-                "GBps": 2 * amp_bytes * v[2] / (v[1] * 1e-3) / 1e9,
-                "TFLOPs": (v[3] / (v[1] * 1e-3) / 1e12) if v[3] else None} for k, v in kinds.items()}
+    """Per kernel: launches, average ms, GB/s of the algorithmic bytes (the
+    amplitudes the plain method updates, read and written once) and, where
+    they differ, of the 128-byte lines the kernel must move (controls on
+    qubits inside a line select half of every line)."""
+    out = {}
+    for k, v in kinds.items():
+        d = {"launches": v[0], "avg_ms": v[1] / v[0], "GBps": 2 * amp_bytes * v[2] / (v[1] * 1e-3) / 1e9,
+             "TFLOPs": (v[3] / (v[1] * 1e-3) / 1e12) if v[3] else None}
+        if len(v) > 4 and v[4] != v[2]:
+            d["GBps_lines"] = 2 * amp_bytes * v[4] / (v[1] * 1e-3) / 1e9
+        out[k] = d
+    return out
 
 
 def roofline(kinds, amp_bytes, workload):
-    name, (launches, ms, amps, flops) = max(kinds.items(), key=lambda kv: kv[1][1])
+    name, v = max(kinds.items(), key=lambda kv: kv[1][1])
+    launches, ms, amps, flops = v[:4]
     avg_s = ms * 1e-3 / launches
     if name.startswith("k_dense_mfma<6>"):
         achieved = flops / launches / avg_s / 1e12
@@ -265,7 +289,7 @@ def pmc_probe(args):
         ops = synth.config5_circuit()
     elif density:
         n = 14
-        ops, _ = synth.config3_circuit()
+        ops, traced = synth.config3_circuit()
     else:
         ops = synth.config2_circuit(num_qubits=n, num_gates=args.gates)
     q = qs.Qureg(n, density=density, precision=args.probe_precision).init_hashed(11)
@@ -274,6 +298,12 @@ def pmc_probe(args):
         circ.specialize()
     circ.apply(q)
     q.sync()
+    if density:
+        # the partial trace over the workload's 7 qubits, into a preallocated output
+        red = qs.Qureg(n - len(traced), density=True, precision=args.probe_precision)
+        for _ in range(3):
+            q.partial_trace(traced, out=red)
+        q.sync()
     print(json.dumps({"pmc_probe": "done", "gates": len(ops), "num_qubits": n,
                       "fuse_k": args.probe_fuse_k, "precision": args.probe_precision,
                       "specialized": circ.specialized}), flush=True)
@@ -655,7 +685,7 @@ def main():
         fused.apply(q64)
         plain.apply(q128)
     t64, kinds64 = timed_region(fused, q64, args.steps, torch)
-    t128, kinds128 = timed_region(plain, q128, args.steps, torch)
+    t128, kinds128 = timed_region(plain, q128, args.steps, torch, lines=line_amps(ops, n, 16))
     t64_plain_launch = time_steps(fused, q64, args.steps, torch)
 
     st = fused.stats()
@@ -713,6 +743,20 @@ def main():
                             "speedup_vs_plain_c128": t128 / tf128}
     del qf128, f128
     torch.cuda.empty_cache()
+    # dense blocks of up to 6 qubits on the FP32 matrix cores (the 6-qubit
+    # blocks are MFMA-bound: 32 flop/B at complex64)
+    if not args.no_workloads:
+        d6 = qs.Circuit(n, ops).compile(6, "c64")
+        q64.init_hashed(seed)
+        d6.apply(q64)
+        td6, kindsd6 = timed_region(d6, q64, max(1, args.steps // 4), torch)
+        result["dense_k6_c64"] = {"value": logical / td6, "ms_per_step": td6 * 1e3,
+                                  "passes": d6.stats()["num_passes"],
+                                  "passes_by_width": d6.stats()["passes_by_width"],
+                                  "roofline": roofline({k: v for k, v in kindsd6.items()
+                                                        if k.startswith("k_dense_mfma<6>")} or kindsd6, 8, workload),
+                                  "per_kernel": per_kernel_table(kindsd6, 8)}
+        del d6
     # the fastest in-house streaming kernel, for reading the roofline fraction
     stream = streaming_ceiling(qs, q64, torch)
     stream["frac_of_peak"] = stream["GBps"] / HBM_PEAK_GBS
