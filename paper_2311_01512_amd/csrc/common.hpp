@@ -153,6 +153,8 @@ uint64_t mfma_block_cap(int k);
 // blockIdx + k gridDim, or one block per tile.
 enum { kTileGridChunk = 0, kTileGridStride = 1, kTileGridPerTile = 2 };
 int tile_grid_policy(int tile_d);
+// Tiles per block under the chunk policy (0: as many blocks as stay resident).
+uint64_t tile_chunk();
 // Waves per SIMD that specialised tile steps are compiled for (bounds their
 // registers).
 int step_waves_per_eu(bool f32);

@@ -249,15 +249,19 @@ struct TileSpan {
 // the caller applies: partner coordinate (t + 256 u) ^ xc, and
 // (-1)^{popc((u ^ xh) & zh)} = (-1)^{popc(xh & zh)} (-1)^{popc(u & zh)}, the
 // second factor summed as a fold over the register bits (one sign per bit).
-template <bool IM, int E>
-__device__ __forceinline__ double term_sum(const double2 *__restrict__ tile, const double2 (&own)[E], uint32_t t,
+// Each product Re or Im of conj(own) partner is formed in the precision of
+// the amplitudes (complex64: FP32, whose tile in LDS is then half the bytes);
+// every sum from there on is FP64.
+template <bool IM, int E, typename R>
+__device__ __forceinline__ double term_sum(const C2<R> *__restrict__ tile, const C2<R> (&own)[E], uint32_t t,
                                            uint32_t xc, uint32_t zh)
 {
     double p[E];
 #pragma unroll
     for (int u = 0; u < E; u++) {
-        const double2 v = tile[(t + 256u * u) ^ xc];
-        p[u] = IM ? own[u].x * v.y - own[u].y * v.x : own[u].x * v.x + own[u].y * v.y;
+        const C2<R> v = tile[(t + 256u * u) ^ xc];
+        const R w = IM ? own[u].x * v.y - own[u].y * v.x : own[u].x * v.x + own[u].y * v.y;
+        p[u] = (double)w;
     }
 #pragma unroll
     for (int h = E / 2; h >= 1; h >>= 1) {
@@ -272,7 +276,7 @@ template <typename R, int E>
 __global__ __launch_bounds__(256) void k_expec_tiles(const C2<R> *__restrict__ a, uint64_t num_tiles, TileSpan sp,
                                                      TileTermSet ts, double *__restrict__ partials)
 {
-    __shared__ double2 tile[256 * E];    // FP64 copy: partners need no conversion per term
+    __shared__ C2<R> tile[256 * E];
     __shared__ double red[kTileTerms][4];
     const uint32_t t = threadIdx.x;
     uint64_t toff = 0;
@@ -292,9 +296,9 @@ __global__ __launch_bounds__(256) void k_expec_tiles(const C2<R> *__restrict__ a
     }
     for (; g < num_tiles; g += gridDim.x) {
         const uint64_t base = insert_zeros(g, sp.plan);
-        double2 own[E];
+        C2<R> own[E];
 #pragma unroll
-        for (int u = 0; u < E; u++) own[u] = make_double2((double)x[u].x, (double)x[u].y);
+        for (int u = 0; u < E; u++) own[u] = x[u];
         __syncthreads();    // the previous tile's reads are done
 #pragma unroll
         for (int u = 0; u < E; u++) tile[t + 256 * u] = own[u];
@@ -319,8 +323,8 @@ __global__ __launch_bounds__(256) void k_expec_tiles(const C2<R> *__restrict__ a
                 const uint32_t xc = ts.xl[n] | (ts.xh[n] << 8);
                 uint32_t zh = ts.zh[n];      // likewise for the fold signs
                 asm volatile("" : "+s"(zh));
-                const double s = ((ts.kind >> n) & 1) ? term_sum<true, E>(tile, own, tv, xc, zh)
-                                                      : term_sum<false, E>(tile, own, tv, xc, zh);
+                const double s = ((ts.kind >> n) & 1) ? term_sum<true, E, R>(tile, own, tv, xc, zh)
+                                                      : term_sum<false, E, R>(tile, own, tv, xc, zh);
                 const uint32_t par = (uint32_t)__popcll(base & ts.yz[n]) + (uint32_t)__popc(ts.xh[n] & ts.zh[n]) +
                                      (uint32_t)__popc(tp & ts.zl[n]);
                 acc[n] += (par & 1) ? -s : s;

@@ -697,8 +697,10 @@ int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev)
         const void *mp = mats;
         int chunk = ta.chunk;
         void *args[] = {&a, &nt, &mp, &chunk};
+        const uint64_t ck = policy == kTileGridChunk ? tile_chunk() : 0;
         const unsigned grid = policy == kTileGridPerTile ? grid_for(nt << (p.tile_d - kRegBits), block)
-                                                          : grid_for(nt, 1, p.jit_grid);
+                              : ck ? grid_for(((nt + ck - 1) / ck) * block, block)
+                                   : grid_for(nt, 1, p.jit_grid);
         QS_HIP(hipModuleLaunchKernel((hipFunction_t)p.jit_fn, grid, 1, 1, block, 1, 1, p.jit_lds, q->stream, args,
                                      nullptr));
         return QS_OK;
@@ -720,8 +722,10 @@ int launch_tile_pass(qs_qureg *q, const Pass &p, const void *dev)
             return fail(QS_E_HIP, "occupancy query for the tile kernel failed");
         it = resident.emplace(key, per_cu * cus).first;
     }
+    const uint64_t ck = policy == kTileGridChunk ? tile_chunk() : 0;
     const unsigned grid = policy == kTileGridPerTile ? grid_for(ta.num_tiles << (p.tile_d - kRegBits), block)
-                                                      : grid_for(ta.num_tiles, 1, (uint64_t)it->second);
+                          : ck ? grid_for(((ta.num_tiles + ck - 1) / ck) * block, block)
+                               : grid_for(ta.num_tiles, 1, (uint64_t)it->second);
     if (q->precision == QS_C64)
         hipLaunchKernelGGL(k_tile_step<float>, dim3(grid), dim3(block), lds, q->stream, (float2 *)q->amps, ta, ph, ops,
                            (const float2 *)mats);

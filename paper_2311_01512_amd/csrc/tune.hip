@@ -5,7 +5,8 @@
 // complex64), QS_MFMA_BLOCKS=<max blocks of the MFMA kernel>,
 // QS_TILE_LOW=<lowest qubits every tile step holds>,
 // QS_STEP_WAVES=<waves per SIMD the specialised tile steps are compiled for>,
-// QS_TILE_GRID=chunk|stride|tiles (tile-step grids: resident blocks each
+// QS_TILE_CHUNK=<tiles per block of the chunk policy; unset: as many blocks
+// as stay resident>, QS_TILE_GRID=chunk|stride|tiles (tile-step grids: resident blocks each
 // walking a run of consecutive tiles, resident blocks walking by a fixed
 // stride, or one block per tile; by default one block per tile for tiles of
 // up to 2^12 amplitudes and a stride for larger ones).
@@ -60,6 +61,19 @@ int step_waves_per_eu(bool f32)
     }();
     if (forced) return forced;
     return f32 ? 6 : 4;
+}
+
+uint64_t tile_chunk()
+{
+    static const uint64_t v = [] {
+        const char *e = std::getenv("QS_TILE_CHUNK");
+        if (e) {
+            const unsigned long long k = std::strtoull(e, nullptr, 10);
+            if (k >= 1 && k <= (1ull << 20)) return (uint64_t)k;
+        }
+        return (uint64_t)0;
+    }();
+    return v;
 }
 
 int tile_grid_policy(int tile_d)

@@ -164,8 +164,7 @@ def test_28_qubit_pauli_sum_by_term(qs):
     """The 20-term Pauli sum at full size (3 tile spans of flip masks, as
     timed) against a second route: each term applied to a copy by the
     Pauli-tensor kernel, then <psi|P psi> by the inner product, the
-    coefficients summed on the host.  Both routes form exact FP64 products
-    of the same amplitudes, so they agree to FP64 rounding of the sums."""
+    coefficients summed on the host."""
     import torch
     n = 28
     rng = np.random.default_rng(20)
@@ -184,7 +183,11 @@ def test_28_qubit_pauli_sum_by_term(qs):
             torch.cuda.synchronize()
             p.apply_pauli_tensor(targs, [int(codes[t, k]) for k in targs])
             want += coeffs[t] * q.inner_product(p)
-        assert abs(got - want) < 1e-11 * np.abs(coeffs).sum(), (prec, got, want)
+        # complex128: both routes form exact FP64 products; complex64 tiles
+        # form each product in FP32 (relative rounding 2^-24 per product,
+        # every sum in FP64), which the complex64 scalar bound covers
+        bound = 1e-11 if prec == "c128" else 1e-5
+        assert abs(got - want) < bound * np.abs(coeffs).sum(), (prec, got, want)
         del q, p
         torch.cuda.empty_cache()
 
