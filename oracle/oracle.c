@@ -114,6 +114,52 @@ static inline void kadd(kahan *k, double x)
     k->s = t;
 }
 
+/* ---- write counting (debug build) --------------------------------------
+ * Built with -DORACLE_COUNT_WRITES, every store of a state amplitude adds
+ * one to a counter, so that tests can compare each routine's writes with
+ * the counts the paper states (Table "alg_summary_table" and the cost
+ * statement of each algorithm's section).  The normal build compiles the
+ * counting out. */
+#ifdef ORACLE_COUNT_WRITES
+static uint64_t g_writes;
+#define WROTE(k)                      \
+    do {                              \
+        _Pragma("omp atomic")         \
+        g_writes += (uint64_t)(k);    \
+    } while (0)
+#else
+#define WROTE(k) \
+    do {         \
+    } while (0)
+#endif
+
+/* 1 when this build counts writes. */
+int oracle_counts_writes(void)
+{
+#ifdef ORACLE_COUNT_WRITES
+    return 1;
+#else
+    return 0;
+#endif
+}
+
+/* Writes counted since the last reset (0 in the normal build). */
+uint64_t oracle_writes(void)
+{
+#ifdef ORACLE_COUNT_WRITES
+    return g_writes;
+#else
+    return 0;
+#endif
+}
+
+void oracle_reset_writes(void)
+{
+#ifdef ORACLE_COUNT_WRITES
+    g_writes = 0;
+#endif
+}
+
 /* ---- statevector gates ------------------------------------------------ */
 
 /*
@@ -157,6 +203,7 @@ int oracle_apply_gate(cplx *psi, int N, const int *ctrls, int nc,
                 for (int l = 0; l < dim; l++)
                     acc += M[(size_t)j * dim + l] * v[l];
                 psi[set_bits(z, targs, nt, (uint64_t)j)] = acc;
+                WROTE(1);
             }
         }
         free(v);
@@ -218,8 +265,10 @@ int oracle_apply_pauli_gadget(cplx *psi, int N, const int *targs,
     const int64_t dim = (int64_t)(1ULL << N);
     if (xy == 0) {
 #pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < dim; i++)
+        for (int64_t i = 0; i < dim; i++) {
             psi[i] = a * psi[i] + I * b * pauli_beta((uint64_t)i, yz, eta) * psi[i];
+            WROTE(1);
+        }
         return OR_OK;
     }
     int lb = 0;
@@ -232,6 +281,7 @@ int oracle_apply_pauli_gadget(cplx *psi, int N, const int *targs,
         cplx ai = psi[i], aj = psi[j];
         psi[i] = a * ai + I * b * pauli_beta(j, yz, eta) * aj;
         psi[j] = a * aj + I * b * pauli_beta(i, yz, eta) * ai;
+        WROTE(2);
     }
     return OR_OK;
 }
@@ -256,6 +306,7 @@ int oracle_apply_swap(cplx *psi, int N, int t1, int t2)
             const cplx tmp = psi[i];
             psi[i] = psi[j];
             psi[j] = tmp;
+            WROTE(2);
         }
     }
     return OR_OK;
@@ -284,6 +335,7 @@ int oracle_apply_pauli_tensor(cplx *psi, int N, const int *targs, const int *pau
     for (int64_t i = 0; i < dim; i++) {
         const uint64_t src = (uint64_t)i ^ xy;
         psi[i] = pauli_beta(src, yz, eta) * old[src];
+        WROTE(1);
     }
     free(old);
     return OR_OK;
@@ -305,6 +357,7 @@ int oracle_apply_phase_gadget(cplx *psi, int N, const int *targs, int n, double 
     for (int64_t i = 0; i < dim; i++) {
         const double s = parity((uint64_t)i & mask) ? -1.0 : 1.0;
         psi[i] *= cexp(I * theta * s);
+        WROTE(1);
     }
     return OR_OK;
 }
@@ -497,6 +550,7 @@ int oracle_partial_trace(const cplx *rho, int N, const int *targs, int n, cplx *
             kadd(&im, cimag(rho[g]));
         }
         out[i] = re.s + I * im.s;
+        WROTE(1);
     }
     return OR_OK;
 }

@@ -15,11 +15,16 @@ _lib = None
 
 
 def lib():
+    """The compiled oracle; the environment variable ORACLE_VARIANT selects
+    the write-counting ("count") or sanitizer ("asan") build for the CPU
+    tests that run it in a subprocess."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC):
-            _build.build()
-        L = C.CDLL(_build.LIB)
+        variant = os.environ.get("ORACLE_VARIANT", "plain")
+        path = _build.lib_path(variant)
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build(variant=variant)
+        L = C.CDLL(path)
         P = C.c_void_p
         i = C.c_int
         d = C.c_double
@@ -54,12 +59,16 @@ def lib():
             "oracle_hashed_amps_at": [i, u64, P, u64, P],
             "oracle_splitmix64_at": [u64, u64],
             "oracle_num_threads": [],
+            "oracle_counts_writes": [],
+            "oracle_reset_writes": [],
         }
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = C.c_int
         L.oracle_splitmix64_at.restype = u64
+        L.oracle_writes.argtypes = []
+        L.oracle_writes.restype = u64
         _lib = L
     return _lib
 
@@ -337,6 +346,19 @@ def splitmix64_at(seed, counter):
 
 def num_threads():
     return int(lib().oracle_num_threads())
+
+
+def counts_writes():
+    return bool(lib().oracle_counts_writes())
+
+
+def writes():
+    """Amplitude writes since reset_writes() (write-counting build only)."""
+    return int(lib().oracle_writes())
+
+
+def reset_writes():
+    lib().oracle_reset_writes()
 
 
 # ---- circuits (drive the routines above op by op) ---------------------------

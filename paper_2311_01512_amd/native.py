@@ -8,7 +8,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqsim.so")
+# QS_LIB may name another build of the same library (the CPU tests load the
+# sanitizer build of the host code this way)
+LIB_PATH = os.environ.get("QS_LIB") or os.path.join(HERE, "libqsim.so")
 HEADER = os.path.join(HERE, "..", "include", "qsim.h")
 
 QS_C64, QS_C128 = 0, 1
