@@ -236,3 +236,53 @@ def test_specialized_density_circuit_c128(qs):
     c.apply(q)
     assert np.array_equal(q.get_amps(), generic)
     assert amp_err(q.get_amps(), oracle.run_ops(rho.copy(), ops, density=True)) < TOL["c128"]
+
+
+def test_circuit_dropped_while_its_steps_are_queued(qs):
+    """A specialised circuit applied several times asynchronously and then
+    destroyed at once: destruction waits for the queued steps before it
+    frees their tables and unloads their kernels, so the result equals that
+    of a circuit kept alive."""
+    import torch
+    banner("circuit dropped with queued steps")
+    n = 22
+    ops = synth.config2_circuit(num_qubits=n, num_gates=300, seed=7)
+    ref = qs.Qureg(n, precision="c64").init_hashed(3)
+    keep = qs.Circuit(n, ops).compile(12, "c64")
+    assert keep.specialize() > 0
+    for _ in range(3):
+        keep.apply(ref)
+    ref.sync()
+    q = qs.Qureg(n, precision="c64").init_hashed(3)
+    c = qs.Circuit(n, ops).compile(12, "c64")
+    assert c.specialize() > 0
+    for _ in range(3):
+        c.apply(q)
+    c.close()          # no sync before: the steps are still queued
+    del c
+    q.sync()
+    assert torch.equal(q.tensor, ref.tensor)
+
+
+def test_circuit_recompiled_while_its_steps_are_queued(qs):
+    """Recompiling and re-specialising a circuit right after queueing its
+    steps: the old tables and kernels stay until those steps have run."""
+    import torch
+    banner("circuit recompiled with queued steps")
+    n = 21
+    ops = synth.config2_circuit(num_qubits=n, num_gates=200, seed=8)
+    ref = qs.Qureg(n, precision="c64").init_hashed(4)
+    keep = qs.Circuit(n, ops).compile(12, "c64")
+    keep.specialize()
+    keep.apply(ref)
+    keep.apply(ref)
+    ref.sync()
+    q = qs.Qureg(n, precision="c64").init_hashed(4)
+    c = qs.Circuit(n, ops).compile(12, "c64")
+    c.specialize()
+    c.apply(q)
+    c.compile(12, "c64")      # frees the tables the queued steps read
+    c.specialize()
+    c.apply(q)
+    q.sync()
+    assert torch.equal(q.tensor, ref.tensor)
