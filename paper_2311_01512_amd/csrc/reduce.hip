@@ -9,6 +9,7 @@
 #include <cmath>
 #include <complex>
 #include <map>
+#include <mutex>
 
 namespace qs {
 
@@ -227,7 +228,7 @@ template <typename R> struct ExpecDM {
 // Block of 256 threads; thread t holds elements t + 256 u, u < E = 2^(d-8);
 // d <= 11 and L = 4 (runs of 16 contiguous amplitudes), so m = 7 masks per span.
 constexpr int kTileTerms = 8;
-constexpr int kTileBlocks = 1024;   // persistent blocks of one launch
+constexpr int kTileBlocks = 4096;   // most blocks of one launch
 
 struct TileTermSet {
     int count;
@@ -237,6 +238,7 @@ struct TileTermSet {
     uint32_t zl[kTileTerms];        // coordinate sign mask, thread bits
     uint32_t zh[kTileTerms];        // coordinate sign mask, register bits
     uint64_t yz[kTileTerms];        // sign mask of the term (tile base parity)
+    int pair[kTileTerms];           // half sums (E = 8): register bit 0-2 or 8 + thread bit; -1: full sum
 };
 
 struct TileSpan {
@@ -249,17 +251,21 @@ struct TileSpan {
 // the caller applies: partner coordinate (t + 256 u) ^ xc, and
 // (-1)^{popc((u ^ xh) & zh)} = (-1)^{popc(xh & zh)} (-1)^{popc(u & zh)}, the
 // second factor summed as a fold over the register bits (one sign per bit).
+// The partner of register u sits at byte tb + su, tb = (t ^ xl) times the
+// element size (the thread's part) and su that of 256 (u ^ xh) (the same for
+// every thread, a scalar): one vector add per LDS read.
 // Each product Re or Im of conj(own) partner is formed in the precision of
 // the amplitudes (complex64: FP32, whose tile in LDS is then half the bytes);
 // every sum from there on is FP64.
 template <bool IM, int E, typename R>
-__device__ __forceinline__ double term_sum(const C2<R> *__restrict__ tile, const C2<R> (&own)[E], uint32_t t,
-                                           uint32_t xc, uint32_t zh)
+__device__ __forceinline__ double term_sum(const unsigned char *__restrict__ tile, const C2<R> (&own)[E], uint32_t tb,
+                                           uint32_t xh, uint32_t zh)
 {
     double p[E];
 #pragma unroll
     for (int u = 0; u < E; u++) {
-        const C2<R> v = tile[(t + 256u * u) ^ xc];
+        const uint32_t su = __builtin_amdgcn_readfirstlane(((uint32_t)u ^ xh) * 256u * (uint32_t)sizeof(C2<R>));
+        const C2<R> v = *(const C2<R> *)(tile + (tb + su));
         const R w = IM ? own[u].x * v.y - own[u].y * v.x : own[u].x * v.x + own[u].y * v.y;
         p[u] = (double)w;
     }
@@ -270,6 +276,84 @@ __device__ __forceinline__ double term_sum(const C2<R> *__restrict__ tile, const
         for (int u = 0; u < h; u++) p[u] = fma(sg, p[u + h], p[u]);
     }
     return p[0];
+}
+
+// Half sums (tiles of 8 registers).  For a Hermitian Pauli string the two
+// products of a pair (i, j = i ^ x) agree once the term's sign is applied:
+// Re (or Im) of conj(a_i) a_j (-1)^{j.z} equals that of conj(a_j) a_i
+// (-1)^{i.z}, because (-1)^{x.z} is +1 exactly for the terms that sum Re.
+// So each pair is taken once, from the element whose pairing bit is clear,
+// and the caller doubles the sum.
+// Register pairing (x flips register bit RB, the lowest of xh): the
+// registers u with bit RB clear, partners u ^ xh; the fold's signs come from
+// the other two register bits.
+template <bool IM, int RB, typename R>
+__device__ __forceinline__ double term_half_reg(const unsigned char *__restrict__ tile, const C2<R> (&own)[8],
+                                                uint32_t tb, uint32_t xh, uint32_t zh)
+{
+    constexpr int ub0 = RB == 0 ? 1 : 0, ub1 = RB == 2 ? 1 : 2;   // register bits of k's bits 0 and 1
+    double p[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int u = ((k >> RB) << (RB + 1)) | (k & ((1 << RB) - 1));
+        const uint32_t su = __builtin_amdgcn_readfirstlane(((uint32_t)u ^ xh) * 256u * (uint32_t)sizeof(C2<R>));
+        const C2<R> v = *(const C2<R> *)(tile + (tb + su));
+        const R w = IM ? own[u].x * v.y - own[u].y * v.x : own[u].x * v.x + own[u].y * v.y;
+        p[k] = (double)w;
+    }
+    const double s1 = ((zh >> ub1) & 1u) ? -1.0 : 1.0, s0 = ((zh >> ub0) & 1u) ? -1.0 : 1.0;
+    p[0] = fma(s1, p[2], p[0]);
+    p[1] = fma(s1, p[3], p[1]);
+    return fma(s0, p[1], p[0]);
+}
+
+// Thread pairing (x flips thread bits only): thread t takes the registers u
+// whose bit 2 equals bit b of t (b a flipped thread bit), its own values read
+// back from LDS: ob, pb = byte offsets of (t, 4 q) and (t ^ xl, 4 q), q that
+// bit of t; the sign of register bit 2 is the caller's.
+template <bool IM, typename R>
+__device__ __forceinline__ double term_half_thr(const unsigned char *__restrict__ tile, uint32_t ob, uint32_t pb,
+                                                uint32_t zh)
+{
+    double p[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const uint32_t off = (uint32_t)k * 256u * (uint32_t)sizeof(C2<R>);
+        const C2<R> o = *(const C2<R> *)(tile + (ob + off));
+        const C2<R> v = *(const C2<R> *)(tile + (pb + off));
+        const R w = IM ? o.x * v.y - o.y * v.x : o.x * v.x + o.y * v.y;
+        p[k] = (double)w;
+    }
+    const double s1 = ((zh >> 1) & 1u) ? -1.0 : 1.0, s0 = (zh & 1u) ? -1.0 : 1.0;
+    p[0] = fma(s1, p[2], p[0]);
+    p[1] = fma(s1, p[3], p[1]);
+    return fma(s0, p[1], p[0]);
+}
+
+// One term over the thread's elements of the tile with its pairing (pr:
+// TileTermSet::pair); extra: a sign bit the caller adds to the term's
+// parity; twice: the sum counts each pair once.
+template <bool IM, int E, typename R>
+__device__ __forceinline__ double term_any(const unsigned char *__restrict__ tile, const C2<R> (&own)[E], uint32_t t,
+                                           uint32_t tp, uint32_t xh, uint32_t zh, int pr, uint32_t &extra,
+                                           bool &twice)
+{
+    constexpr uint32_t sz = (uint32_t)sizeof(C2<R>);
+    if constexpr (E == 8) {
+        if (pr >= 8) {
+            const uint32_t q = (t >> (pr - 8)) & 1u;
+            extra = q & (zh >> 2);
+            twice = true;
+            return term_half_thr<IM, R>(tile, (t + 1024u * q) * sz, (tp + 1024u * q) * sz, zh);
+        }
+        if (pr >= 0) {
+            twice = true;
+            if (pr == 0) return term_half_reg<IM, 0, R>(tile, own, tp * sz, xh, zh);
+            if (pr == 1) return term_half_reg<IM, 1, R>(tile, own, tp * sz, xh, zh);
+            return term_half_reg<IM, 2, R>(tile, own, tp * sz, xh, zh);
+        }
+    }
+    return term_sum<IM, E, R>(tile, own, tp * sz, xh, zh);
 }
 
 template <typename R, int E>
@@ -320,14 +404,19 @@ __global__ __launch_bounds__(256) void k_expec_tiles(const C2<R> *__restrict__ a
         for (int n = 0; n < kTileTerms; n++) {
             if (n < ts.count) {
                 const uint32_t tp = tv ^ ts.xl[n];
-                const uint32_t xc = ts.xl[n] | (ts.xh[n] << 8);
                 uint32_t zh = ts.zh[n];      // likewise for the fold signs
                 asm volatile("" : "+s"(zh));
-                const double s = ((ts.kind >> n) & 1) ? term_sum<true, E, R>(tile, own, tv, xc, zh)
-                                                      : term_sum<false, E, R>(tile, own, tv, xc, zh);
+                const unsigned char *tl = reinterpret_cast<const unsigned char *>(tile);
+                uint32_t extra = 0;
+                bool twice = false;
+                const double s =
+                    ((ts.kind >> n) & 1)
+                        ? term_any<true, E, R>(tl, own, tv, tp, ts.xh[n], zh, ts.pair[n], extra, twice)
+                        : term_any<false, E, R>(tl, own, tv, tp, ts.xh[n], zh, ts.pair[n], extra, twice);
                 const uint32_t par = (uint32_t)__popcll(base & ts.yz[n]) + (uint32_t)__popc(ts.xh[n] & ts.zh[n]) +
-                                     (uint32_t)__popc(tp & ts.zl[n]);
-                acc[n] += (par & 1) ? -s : s;
+                                     (uint32_t)__popc(tp & ts.zl[n]) + extra;
+                const double w = twice ? 2.0 : 1.0;
+                acc[n] = fma((par & 1) ? -w : w, s, acc[n]);
             }
         }
     }
@@ -644,6 +733,34 @@ static int expec_sv(qs_qureg *q, const int *codes, const double *coeffs, int T, 
     return QS_OK;
 }
 
+// Blocks of one k_expec_tiles<R, E> launch: twice as many as stay resident
+// (at most kTileBlocks), each walking tiles by a fixed stride.  On the
+// 20-term sum over 28 qubits, against 1024 blocks: complex64 1.60 against
+// 1.76 ms per call (as many as stay resident: 1.65 ms), complex128 2.41
+// against 2.66 ms; runs of consecutive tiles per block were no faster.
+template <typename R>
+static int expec_tile_blocks(int E, int device)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(device, E);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    hipError_t e1;
+    if (E == 1) e1 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_expec_tiles<R, 1>, 256, 0);
+    else if (E == 2) e1 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_expec_tiles<R, 2>, 256, 0);
+    else if (E == 4) e1 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_expec_tiles<R, 4>, 256, 0);
+    else e1 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_expec_tiles<R, 8>, 256, 0);
+    const hipError_t e2 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    int blocks = 1024;
+    if (e1 == hipSuccess && e2 == hipSuccess && per_cu >= 1 && cus >= 1) blocks = std::min(kTileBlocks, 2 * per_cu * cus);
+    else (void)hipGetLastError();
+    cache.emplace(key, blocks);
+    return blocks;
+}
+
 template <typename R>
 static void launch_expec_tiles(int E, int blocks, hipStream_t st, const C2<R> *amps, uint64_t num_tiles,
                                const TileSpan &sp, const TileTermSet &ts, double *partials)
@@ -778,7 +895,7 @@ static int expec_sv_tiles(qs_qureg *q, const int *codes, const double *coeffs, i
         for (uint64_t x : chosen)
             for (int t : by_mask[x]) terms.push_back(t);
         const uint64_t num_tiles = 1ULL << (N - d);
-        const int blocks = (int)std::min<uint64_t>(num_tiles, kTileBlocks);
+        const int blocks = (int)std::min<uint64_t>(num_tiles, (uint64_t)expec_tile_blocks<R>(E, q->device));
         for (size_t b0 = 0; b0 < terms.size(); b0 += kTileTerms) {
             TileTermSet ts{};
             ts.count = (int)std::min<size_t>(kTileTerms, terms.size() - b0);
@@ -794,6 +911,11 @@ static int expec_sv_tiles(qs_qureg *q, const int *codes, const double *coeffs, i
                 ts.zl[n] = zc & 255u;
                 ts.zh[n] = zc >> 8;
                 ts.yz[n] = yzs[t];
+                // pairing of the half sums: the lowest flipped register bit,
+                // else the highest flipped thread bit (tiles of 8 registers)
+                ts.pair[n] = -1;
+                if (E == 8 && ts.xh[n]) ts.pair[n] = __builtin_ctz(ts.xh[n]);
+                else if (E == 8 && ts.xl[n]) ts.pair[n] = 8 + (31 - __builtin_clz(ts.xl[n]));
                 if (__builtin_popcountll(xs[t] & yzs[t]) & 1) ts.kind |= 1u << n;
                 slot_term.push_back(t);
             }
