@@ -565,14 +565,15 @@ def bench_batch(args, torch, qs, synth):
     # algorithmic FP32 flops of one run: a single-qubit operator is a 2 x 2
     # complex matrix on every amplitude (14 flops per amplitude: two complex
     # products and a sum), CZ none; the adjoint sweep applies each operator
-    # to two states and forms conj(lambda) P phi (8 flops per amplitude) for
-    # every rotation; lambda = H psi costs 8 flops per amplitude and term
+    # to two states and forms Im conj(lambda) P phi (4 flops per amplitude:
+    # the gradient needs no real part) for every rotation; lambda = H psi
+    # costs 8 flops per amplitude and term
     flops = 0
     for p in probs:
         a = 1 << p["num_qubits"]
         one_q = sum(1 for op in p["ops"] if op["op"] == "gadget" or not op.get("ctrls"))
         rot = sum(1 for op in p["ops"] if op["op"] == "gadget" and "param" in op)
-        flops += a * (14 * one_q + 2 * 14 * one_q + 8 * rot + 8 * len(p["coeffs"]))
+        flops += a * (14 * one_q + 2 * 14 * one_q + 4 * rot + 8 * len(p["coeffs"]))
     achieved = flops / full / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,

@@ -265,7 +265,8 @@ __global__ __launch_bounds__(256) void k_batch_forward(C2<R> *__restrict__ amps,
 }
 
 // Adjoint sweep over one tile of phi and lambda: for each operator, last
-// first, the rotation's partial <lambda|P|phi> over the tile, then
+// first, the rotation's partial Im <lambda|P|phi> over the tile (the
+// gradient -2 s Im <lambda|P|phi> needs no real part), then
 // phi <- U^dagger phi and lambda <- U^dagger lambda.  For a rotation both
 // happen in one pass over the pairs (j0, j1) it couples; each wavefront
 // reduces its share in FP64 and leaves it in LDS, and thread 0 adds the
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(256) void k_batch_backward(C2<R> *__restrict__ amps
                                                          const double *__restrict__ trig, double *__restrict__ gpart)
 {
     extern __shared__ unsigned char lds_raw[];
-    __shared__ double red[2][8];   // two rotations in flight, (re, im) of up to 4 wavefronts
+    __shared__ double red[2][4];   // two rotations in flight, Im of up to 4 wavefronts
     const uint2 w = work[blockIdx.x];
     const DStep &st = steps[w.x];
     const int T = 1 << st.qn;
@@ -298,13 +299,9 @@ __global__ __launch_bounds__(256) void k_batch_backward(C2<R> *__restrict__ amps
     int pslot = 0;
     auto flush = [&]() {
         if (pend != ~0ULL && threadIdx.x == 0) {
-            double re = 0.0, im = 0.0;
-            for (int v = 0; v < nwaves; v++) {
-                re += red[pslot][2 * v];
-                im += red[pslot][2 * v + 1];
-            }
-            gpart[2 * pend] = re;
-            gpart[2 * pend + 1] = im;
+            double im = 0.0;
+            for (int v = 0; v < nwaves; v++) im += red[pslot][v];
+            gpart[pend] = im;
         }
         pend = ~0ULL;
     };
@@ -322,7 +319,7 @@ __global__ __launch_bounds__(256) void k_batch_backward(C2<R> *__restrict__ amps
                 tile_gate<R>(lam, st.qn, op.pos0, u);
             } else {
                 const int pos = op.pos0, lo = (1 << pos) - 1, np = T >> 1;
-                double re = 0.0, im = 0.0;
+                double im = 0.0;
                 for (int p = threadIdx.x; p < np; p += blockDim.x) {
                     const int j0 = (p & lo) | ((p & ~lo) << 1), j1 = j0 | (1 << pos);
                     const C2<R> f0 = phi[j0], f1 = phi[j1], y0 = lam[j0], y1 = lam[j1];
@@ -337,7 +334,6 @@ __global__ __launch_bounds__(256) void k_batch_backward(C2<R> *__restrict__ amps
                         p0 = f0;
                         p1 = mk<R>(-f1.x, -f1.y);
                     }
-                    re += (double)y0.x * p0.x + (double)y0.y * p0.y + (double)y1.x * p1.x + (double)y1.y * p1.y;
                     im += (double)y0.x * p0.y - (double)y0.y * p0.x + (double)y1.x * p1.y - (double)y1.y * p1.x;
                     C2<R> g0 = mk<R>(0, 0), g1 = mk<R>(0, 0), h0 = mk<R>(0, 0), h1 = mk<R>(0, 0);
                     cmac<R>(g0, u[0], f0);
@@ -353,13 +349,9 @@ __global__ __launch_bounds__(256) void k_batch_backward(C2<R> *__restrict__ amps
                     lam[j0] = h0;
                     lam[j1] = h1;
                 }
-                re = bwave_sum(re);
                 im = bwave_sum(im);
                 pslot = k & 1;
-                if (lane == 0) {
-                    red[pslot][2 * wave] = re;
-                    red[pslot][2 * wave + 1] = im;
-                }
+                if (lane == 0) red[pslot][wave] = im;
                 pend = op.gpart + w.y;
             }
         }
@@ -415,11 +407,10 @@ __device__ __forceinline__ void reg_pairs(C2<R> (&x)[8], C2<R> m0, C2<R> m1, C2<
     else asm volatile("; reg pairs 2");
 }
 
-// Partial of <lambda|P|phi> over the register pairs (u0, u0 | 1 << J) of a
+// Partial of Im <lambda|P|phi> over the register pairs (u0, u0 | 1 << J) of a
 // rotation exp(i theta P) on register bit J.
 template <typename R, int J>
-__device__ __forceinline__ void reg_grad_pairs(const C2<R> (&x)[8], const C2<R> (&y)[8], int pauli, double &re,
-                                               double &im)
+__device__ __forceinline__ void reg_grad_pairs(const C2<R> (&x)[8], const C2<R> (&y)[8], int pauli, double &im)
 {
 #pragma unroll
     for (int u0 = 0; u0 < 8; u0++) {
@@ -441,10 +432,8 @@ __device__ __forceinline__ void reg_grad_pairs(const C2<R> (&x)[8], const C2<R> 
             // complex64 states: the pair's products in FP32 (relative error
             // about 1e-7, below the states' own), the sums over lanes, waves
             // and tiles in FP64
-            re += (double)(l0.x * p0.x + l0.y * p0.y + l1.x * p1.x + l1.y * p1.y);
             im += (double)(l0.x * p0.y - l0.y * p0.x + l1.x * p1.y - l1.y * p1.x);
         } else {
-            re += (double)l0.x * p0.x + (double)l0.y * p0.y + (double)l1.x * p1.x + (double)l1.y * p1.y;
             im += (double)l0.x * p0.y - (double)l0.y * p0.x + (double)l1.x * p1.y - (double)l1.y * p1.x;
         }
     }
@@ -561,7 +550,7 @@ __global__ __launch_bounds__(512) void k_batch_forward_reg(C2<R> *__restrict__ a
 }
 
 // Adjoint sweep on registers: phases and operators last first; a rotation's
-// partial <lambda|P|phi> comes from the register pairs it couples, before
+// partial Im <lambda|P|phi> comes from the register pairs it couples, before
 // U^dagger is applied to both states.  Each wavefront leaves its partial in
 // the rotation's LDS slot; thread 0 adds the wavefronts' partials (fixed
 // order) after the next barrier.
@@ -575,7 +564,7 @@ __global__ __launch_bounds__(512) void k_batch_backward_reg(C2<R> *__restrict__ 
                                                              double *__restrict__ gpart)
 {
     extern __shared__ unsigned char lds_raw[];
-    __shared__ double red[kPhaseRotMax][8][2];
+    __shared__ double red[kPhaseRotMax][8];
     const uint2 w = work[blockIdx.x];
     const DStep &st = steps[w.x];
     const uint64_t base = insert_zeros(w.y, st.plan);
@@ -603,17 +592,17 @@ __global__ __launch_bounds__(512) void k_batch_backward_reg(C2<R> *__restrict__ 
     }
     int pend_phase = -1;   // phase whose rotation partials sit in red
     // the finished phase's partials summed over the waves, one thread per
-    // operator and component (the reads complete before the barrier that
+    // operator (the reads complete before the barrier that
     // precedes the next writes to red)
     auto flush = [&]() {
         if (pend_phase >= 0) {
             const BPhase &D = phases[pend_phase];
-            for (int i = (int)t; i < 2 * (D.op_end - D.op_begin); i += (int)blockDim.x) {
-                const DOp &op = ops[D.op_begin + (i >> 1)];
+            for (int i = (int)t; i < D.op_end - D.op_begin; i += (int)blockDim.x) {
+                const DOp &op = ops[D.op_begin + i];
                 if (op.grad < 0) continue;
                 double v = 0.0;
-                for (int v2 = 0; v2 < nwaves; v2++) v += red[op.slot][v2][i & 1];
-                gpart[2 * (op.gpart + w.y) + (i & 1)] = v;
+                for (int v2 = 0; v2 < nwaves; v2++) v += red[op.slot][v2];
+                gpart[op.gpart + w.y] = v;
             }
         }
         pend_phase = -1;
@@ -655,18 +644,14 @@ __global__ __launch_bounds__(512) void k_batch_backward_reg(C2<R> *__restrict__ 
             C2<R> u[4];
             op_matrix<R>(op, trig + 2 * k, -1, u);
             if (op.grad >= 0) {
-                double re = 0.0, im = 0.0;
+                double im = 0.0;
                 switch (op.rbit) {
-                case 0: reg_grad_pairs<R, 0>(x, y, op.pauli, re, im); break;
-                case 1: reg_grad_pairs<R, 1>(x, y, op.pauli, re, im); break;
-                default: reg_grad_pairs<R, 2>(x, y, op.pauli, re, im); break;
+                case 0: reg_grad_pairs<R, 0>(x, y, op.pauli, im); break;
+                case 1: reg_grad_pairs<R, 1>(x, y, op.pauli, im); break;
+                default: reg_grad_pairs<R, 2>(x, y, op.pauli, im); break;
                 }
-                re = bwave_sum(re);
                 im = bwave_sum(im);
-                if (lane == 0) {
-                    red[op.slot][wave][0] = re;
-                    red[op.slot][wave][1] = im;
-                }
+                if (lane == 0) red[op.slot][wave] = im;
             }
             reg_gate<R>(x, op.rbit, u);
             reg_gate<R>(y, op.rbit, u);
@@ -761,13 +746,9 @@ __global__ __launch_bounds__(256) void k_batch_grad(const double *__restrict__ g
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= num_rot) return;
-    double re = 0.0, im = 0.0;
-    for (uint64_t t = first[r]; t < first[r + 1]; t++) {
-        re += gpart[2 * t];
-        im += gpart[2 * t + 1];
-    }
-    out[2 * r] = re;
-    out[2 * r + 1] = im;
+    double im = 0.0;
+    for (uint64_t t = first[r]; t < first[r + 1]; t++) im += gpart[t];
+    out[r] = im;
 }
 
 }  // namespace qs
@@ -1499,13 +1480,13 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
     if (rc != QS_OK) return rc;
     if ((rc = upload(&b->d_epart, nullptr, sizeof(double) * 2 * bm_circ.size())) != QS_OK) return rc;
     if ((rc = upload(&b->d_energy, nullptr, sizeof(double) * 2 * b->circs.size())) != QS_OK) return rc;
-    if ((rc = upload(&b->d_gpart, nullptr, sizeof(double) * 2 * gfirst.back())) != QS_OK) return rc;
-    if ((rc = upload(&b->d_gop, nullptr, sizeof(double) * 2 * std::max(1, b->num_rot))) != QS_OK) return rc;
+    if ((rc = upload(&b->d_gpart, nullptr, sizeof(double) * std::max<uint64_t>(1, gfirst.back()))) != QS_OK) return rc;
+    if ((rc = upload(&b->d_gop, nullptr, sizeof(double) * std::max(1, b->num_rot))) != QS_OK) return rc;
     if ((rc = upload(&b->d_params, nullptr, sizeof(double) * std::max(1, b->total_params))) != QS_OK) return rc;
     b->num_ops = (int)ops.size();
     if ((rc = upload(&b->d_trig, nullptr, sizeof(double) * 2 * std::max(1, b->num_ops))) != QS_OK) return rc;
     if (hipHostMalloc(&b->h_energy, sizeof(double) * 2 * b->circs.size(), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&b->h_gop, sizeof(double) * 2 * std::max(1, b->num_rot), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&b->h_gop, sizeof(double) * std::max(1, b->num_rot), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&b->h_params, sizeof(double) * std::max(1, b->total_params), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         return fail(QS_E_ALLOC, "pinned host allocation failed");
@@ -1539,14 +1520,14 @@ int qs_batch_run(qs_batch *b, const double *params, double *energies, double *gr
     QS_HIP(hipMemcpyAsync(b->h_energy, b->d_energy, sizeof(double) * 2 * b->circs.size(), hipMemcpyDeviceToHost,
                           b->stream));
     if (want_grads && b->num_rot > 0)
-        QS_HIP(hipMemcpyAsync(b->h_gop, b->d_gop, sizeof(double) * 2 * b->num_rot, hipMemcpyDeviceToHost, b->stream));
+        QS_HIP(hipMemcpyAsync(b->h_gop, b->d_gop, sizeof(double) * b->num_rot, hipMemcpyDeviceToHost, b->stream));
     QS_HIP(hipStreamSynchronize(b->stream));
     if (energies)
         for (size_t c = 0; c < b->circs.size(); c++) energies[c] = b->h_energy[2 * c];
     if (want_grads) {
         for (int p = 0; p < b->total_params; p++) grads[p] = 0.0;
         // dE/dtheta_p += 2 Re(i scale <lambda|P|phi>) = -2 scale Im<lambda|P|phi>
-        for (int r = 0; r < b->num_rot; r++) grads[b->rot_param[r]] += -2.0 * b->rot_scale[r] * b->h_gop[2 * r + 1];
+        for (int r = 0; r < b->num_rot; r++) grads[b->rot_param[r]] += -2.0 * b->rot_scale[r] * b->h_gop[r];
     }
     b->last_run_had_grads = want_grads;
     return QS_OK;
