@@ -442,6 +442,53 @@ __device__ __forceinline__ void reg_grad_pairs(const C2<R> (&x)[8], const C2<R> 
     else asm volatile("; grad pairs 2");
 }
 
+// Rotation c 1 + i s P (P = X, Y, Z by PA = 1, 2, 3) on the register pairs
+// (u0, u0 | 1 << J): the matrix's zeros and its real or imaginary entries
+// spelled out, 8 FP operations per pair instead of a general 2 x 2
+// complex product's 16.
+template <typename R, int J, int PA>
+__device__ __forceinline__ void reg_rot_pairs(C2<R> (&x)[8], R c, R s)
+{
+#pragma unroll
+    for (int u0 = 0; u0 < 8; u0++) {
+        if ((u0 >> J) & 1) continue;
+        const C2<R> a = x[u0], b = x[u0 | (1 << J)];
+        if constexpr (PA == 1) {          // (c a + i s b, i s a + c b)
+            x[u0] = mk<R>(c * a.x - s * b.y, c * a.y + s * b.x);
+            x[u0 | (1 << J)] = mk<R>(c * b.x - s * a.y, c * b.y + s * a.x);
+        } else if constexpr (PA == 2) {   // (c a + s b, c b - s a)
+            x[u0] = mk<R>(c * a.x + s * b.x, c * a.y + s * b.y);
+            x[u0 | (1 << J)] = mk<R>(c * b.x - s * a.x, c * b.y - s * a.y);
+        } else {                          // ((c + i s) a, (c - i s) b)
+            x[u0] = mk<R>(c * a.x - s * a.y, c * a.y + s * a.x);
+            x[u0 | (1 << J)] = mk<R>(c * b.x + s * b.y, c * b.y - s * b.x);
+        }
+    }
+    // distinct empty statements, as in reg_pairs
+    if constexpr (J == 0) asm volatile("; rot pairs 0");
+    else if constexpr (J == 1) asm volatile("; rot pairs 1");
+    else asm volatile("; rot pairs 2");
+}
+
+template <typename R, int PA>
+__device__ __forceinline__ void reg_rot_p(C2<R> (&x)[8], int rbit, R c, R s)
+{
+    switch (rbit) {
+    case 0: reg_rot_pairs<R, 0, PA>(x, c, s); break;
+    case 1: reg_rot_pairs<R, 1, PA>(x, c, s); break;
+    default: reg_rot_pairs<R, 2, PA>(x, c, s); break;
+    }
+}
+
+// A rotation exp(i theta P) (s = dir sin(theta)) on register bit rbit.
+template <typename R>
+__device__ __forceinline__ void reg_rot(C2<R> (&x)[8], int rbit, int pauli, R c, R s)
+{
+    if (pauli == 1) reg_rot_p<R, 1>(x, rbit, c, s);
+    else if (pauli == 2) reg_rot_p<R, 2>(x, rbit, c, s);
+    else reg_rot_p<R, 3>(x, rbit, c, s);
+}
+
 template <typename R>
 __device__ __forceinline__ void reg_gate(C2<R> (&x)[8], int rbit, const C2<R> (&u)[4])
 {
@@ -534,6 +581,8 @@ __global__ __launch_bounds__(512) void k_batch_forward_reg(C2<R> *__restrict__ a
             const DOp &op = ops[k];
             if (op.kind == BOP_CZ) {
                 reg_cz<R>(x, op, tau, P, base);
+            } else if (op.kind == BOP_ROT) {
+                reg_rot<R>(x, op.rbit, op.pauli, (R)trig[2 * k], (R)trig[2 * k + 1]);
             } else {
                 C2<R> u[4];
                 op_matrix<R>(op, trig + 2 * k, +1, u);
@@ -653,8 +702,14 @@ __global__ __launch_bounds__(512) void k_batch_backward_reg(C2<R> *__restrict__ 
                 im = bwave_sum(im);
                 if (lane == 0) red[op.slot][wave] = im;
             }
-            reg_gate<R>(x, op.rbit, u);
-            reg_gate<R>(y, op.rbit, u);
+            if (op.kind == BOP_ROT) {
+                const R c = (R)trig[2 * k], sn = -(R)trig[2 * k + 1];   // the adjoint
+                reg_rot<R>(x, op.rbit, op.pauli, c, sn);
+                reg_rot<R>(y, op.rbit, op.pauli, c, sn);
+            } else {
+                reg_gate<R>(x, op.rbit, u);
+                reg_gate<R>(y, op.rbit, u);
+            }
         }
         pend_phase = p;
     }
