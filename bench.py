@@ -723,12 +723,12 @@ def main():
         "reductions_c128": bench_reductions(q128, torch, 16),
         "reductions_c64": bench_reductions(q64, torch, 8),
     }
-    # fused complex128: tile steps at the widest complex128 tile, specialised
+    # fused complex128: tile steps, width autotuned, specialised
     del q128
     torch.cuda.empty_cache()
     f128 = qs.Circuit(n, ops)
     qf128 = qs.Qureg(n, precision="c128")
-    k128, tune128, spec128 = autotune(f128, qf128, (0, 9, 10, 11), args)
+    k128, tune128, spec128 = autotune(f128, qf128, (0, 10, 11, 12, 13), args)
     qf128.init_hashed(seed)
     f128.apply(qf128)
     torch.cuda.synchronize()

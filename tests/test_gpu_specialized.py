@@ -19,7 +19,7 @@ def qs():
     return pkg
 
 
-@pytest.mark.parametrize("prec,k", [("c64", 12), ("c128", 11), ("c64", 10)])
+@pytest.mark.parametrize("prec,k", [("c64", 12), ("c128", 11), ("c64", 10), ("c128", 12), ("c128", 13)])
 def test_specialized_equals_generic_and_oracle(qs, prec, k):
     banner(f"specialised tiles {prec} k={k}")
     N = 14
@@ -40,7 +40,7 @@ def test_specialized_equals_generic_and_oracle(qs, prec, k):
 
 
 @pytest.mark.parametrize("N,k,prec,seed", [(24, 12, "c64", 11), (22, 10, "c64", 5), (20, 13, "c64", 11),
-                                           (24, 11, "c128", 11)])
+                                           (24, 11, "c128", 11), (23, 12, "c128", 7), (22, 13, "c128", 11)])
 def test_every_specialized_pass_equals_generic(qs, N, k, prec, seed):
     """Each step of a 500-gate circuit on a state with many tiles, applied by
     its own kernel and by the generic one to the same input, bit for bit.
