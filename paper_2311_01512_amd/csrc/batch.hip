@@ -52,7 +52,10 @@ struct DOp {
     int param;        // global parameter index (rotations)
     int grad;         // rotation slot, -1 for other operators
     uint64_t gpart;   // first gradient partial of this rotation (one per tile)
-    int rbit;         // register bit of a 1-qubit operator in its phase (register path)
+    int rbit;         // register bit of a 1-qubit operator in its phase (register path); for
+                      // a CZ, of q0, or -1 where q0 is not a register coordinate
+    int rbit1;        // a CZ's register bit of q1, or -1
+    int czrun;        // register path, CZ: bit 0 first, bit 1 last of a run of CZs in its phase
     int slot;         // gradient slot of a rotation within its phase (register path)
     double scale;
     double m[8];      // fixed gate, row-major (re, im)
@@ -499,17 +502,40 @@ __device__ __forceinline__ void reg_gate(C2<R> (&x)[8], int rbit, const C2<R> (&
     }
 }
 
-// CZ: sign flip where both qubits are 1 (a qubit outside the tile reads the
-// tile's base bit).
+// CZ on the register path.  Which of a thread's 8 registers a CZ negates is
+// an 8-bit mask over u: a qubit held in register bit j selects the registers
+// with bit j of u set (0xAA, 0xCC, 0xF0), a qubit on a thread coordinate is 1
+// for all 8 registers or none, a qubit outside the tile reads the tile's base
+// bit; the CZ negates where both are 1.  CZs are diagonal and commute with
+// each other, so a run of them is one mask (the xor of theirs) and one pass
+// of sign flips.
+__device__ __forceinline__ uint32_t cz_side(int pos, int rb, int q, uint32_t tau, uint64_t base)
+{
+    if (rb >= 0) return rb == 0 ? 0xAAu : (rb == 1 ? 0xCCu : 0xF0u);
+    if (pos >= 0) return 0u - ((tau >> pos) & 1u);
+    return ((base >> q) & 1ULL) ? 0xFFu : 0u;
+}
+
+__device__ __forceinline__ uint32_t cz_mask(const DOp &op, uint32_t tau, uint64_t base)
+{
+    return cz_side(op.pos0, op.rbit, op.q0, tau, base) & cz_side(op.pos1, op.rbit1, op.q1, tau, base);
+}
+
+__device__ __forceinline__ float flip_sign(float v, uint32_t s) { return __uint_as_float(__float_as_uint(v) ^ s); }
+
+__device__ __forceinline__ double flip_sign(double v, uint32_t s)
+{
+    return __longlong_as_double(__double_as_longlong(v) ^ (long long)((uint64_t)s << 32));
+}
+
+// Negates register u where bit u of mask is set (the sign bit flipped).
 template <typename R>
-__device__ __forceinline__ void reg_cz(C2<R> (&x)[8], const DOp &op, uint32_t tau, const BPhase &ph, uint64_t base)
+__device__ __forceinline__ void reg_sign(C2<R> (&x)[8], uint32_t mask)
 {
 #pragma unroll
     for (int u = 0; u < 8; u++) {
-        const uint32_t c = tau | bphase_rho(u, ph);
-        const uint32_t b0 = op.pos0 >= 0 ? (c >> op.pos0) & 1u : (uint32_t)((base >> op.q0) & 1ULL);
-        const uint32_t b1 = op.pos1 >= 0 ? (c >> op.pos1) & 1u : (uint32_t)((base >> op.q1) & 1ULL);
-        if (b0 & b1) x[u] = mk<R>(-x[u].x, -x[u].y);
+        const uint32_t s = (mask << (31 - u)) & 0x80000000u;
+        x[u] = mk<R>(flip_sign(x[u].x, s), flip_sign(x[u].y, s));
     }
 }
 
@@ -577,10 +603,15 @@ __global__ __launch_bounds__(512) void k_batch_forward_reg(C2<R> *__restrict__ a
             tau = tn;
         }
         if (!active) continue;
+        uint32_t czm = 0;   // sign mask of the current run of CZs
         for (int k = P.op_begin; k < P.op_end; k++) {
             const DOp &op = ops[k];
             if (op.kind == BOP_CZ) {
-                reg_cz<R>(x, op, tau, P, base);
+                czm ^= cz_mask(op, tau, base);
+                if (op.czrun & 2) {   // the run's last CZ
+                    reg_sign<R>(x, czm);
+                    czm = 0;
+                }
             } else if (op.kind == BOP_ROT) {
                 reg_rot<R>(x, op.rbit, op.pauli, (R)trig[2 * k], (R)trig[2 * k + 1]);
             } else {
@@ -683,11 +714,16 @@ __global__ __launch_bounds__(512) void k_batch_backward_reg(C2<R> *__restrict__ 
             tau = tn;
         }
         if (!active) continue;
+        uint32_t czm = 0;   // sign mask of the current run of CZs
         for (int k = P.op_end - 1; k >= P.op_begin; k--) {
             const DOp &op = ops[k];
             if (op.kind == BOP_CZ) {
-                reg_cz<R>(x, op, tau, P, base);
-                reg_cz<R>(y, op, tau, P, base);
+                czm ^= cz_mask(op, tau, base);
+                if (op.czrun & 1) {   // the run's first CZ, reached last
+                    reg_sign<R>(x, czm);
+                    reg_sign<R>(y, czm);
+                    czm = 0;
+                }
                 continue;
             }
             C2<R> u[4];
@@ -1379,6 +1415,7 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
                     x.m[2 * m + 1] = o.m[m].imag();
                 }
                 x.grad = -1;
+                x.rbit = x.rbit1 = -1;
                 if (o.kind == BOP_ROT) {
                     x.grad = (int)b->rot_param.size();
                     x.gpart = gfirst.back();
@@ -1437,9 +1474,41 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
                         ph.rc[j] = R[j];
                         ph.lo[j] = (1u << sorted_r[j]) - 1u;
                     }
-                    for (size_t kk = first; kk < out.size(); kk++)
-                        if (out[kk].kind != BOP_CZ)
-                            out[kk].rbit = (int)(std::find(R.begin(), R.end(), out[kk].pos0) - R.begin());
+                    auto rbit_of = [&](int pos) {
+                        auto it = std::find(R.begin(), R.end(), pos);
+                        return it == R.end() ? -1 : (int)(it - R.begin());
+                    };
+                    for (size_t kk = first; kk < out.size(); kk++) {
+                        out[kk].rbit = rbit_of(out[kk].pos0);
+                        out[kk].rbit1 = out[kk].kind == BOP_CZ ? rbit_of(out[kk].pos1) : -1;
+                    }
+                    // a CZ joins the phase's previous run of CZs when it
+                    // commutes with every operator between them (no shared
+                    // qubit, or a Z rotation: diagonal), so that the kernels
+                    // apply each run as one sign mask
+                    {
+                        std::vector<DOp> ord;
+                        for (size_t kk = first; kk < out.size(); kk++) {
+                            const DOp &x = out[kk];
+                            size_t at = ord.size();
+                            if (x.kind == BOP_CZ) {
+                                size_t j = ord.size();
+                                while (j > 0 && ord[j - 1].kind != BOP_CZ) {
+                                    const DOp &o = ord[j - 1];
+                                    if ((support(o) & support(x)) && !(o.kind == BOP_ROT && o.pauli == 3)) break;
+                                    j--;
+                                }
+                                if (j > 0 && ord[j - 1].kind == BOP_CZ) at = j;
+                            }
+                            ord.insert(ord.begin() + (long)at, x);
+                        }
+                        for (size_t kk = 0; kk < ord.size(); kk++) {
+                            if (ord[kk].kind != BOP_CZ) continue;
+                            ord[kk].czrun = (kk == 0 || ord[kk - 1].kind != BOP_CZ ? 1 : 0) |
+                                            (kk + 1 == ord.size() || ord[kk + 1].kind != BOP_CZ ? 2 : 0);
+                        }
+                        std::copy(ord.begin(), ord.end(), out.begin() + (long)first);
+                    }
                     phases.push_back(ph);
                 }
                 std::copy(out.begin(), out.end(), ops.begin() + d.op_begin);

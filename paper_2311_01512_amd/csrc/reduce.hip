@@ -919,7 +919,6 @@ static int expec_sv_tiles(qs_qureg *q, const int *codes, const double *coeffs, i
                 if (__builtin_popcountll(xs[t] & yzs[t]) & 1) ts.kind |= 1u << n;
                 slot_term.push_back(t);
             }
-            const C2<R> *amps = (const C2<R> *)q->amps;
             launch_expec_tiles<R>(E, blocks, q->stream, (const C2<R> *)q->amps, num_tiles, sp, ts, q->d_partials);
             QS_LAUNCH_CHECK();
             hipLaunchKernelGGL(k_finalize_terms, dim3(ts.count), dim3(256), 0, q->stream,
