@@ -550,30 +550,49 @@ def bench_batch(args, torch, qs, synth):
     b.compile()
     st = b.stats()
     params = np.concatenate([p["angles"] for p in probs])
-    for _ in range(args.warmup):
-        b.run(params, grads=True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e, g = b.run(params, grads=True)
-    full = (time.perf_counter() - t0) / args.steps
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        b.run(params, grads=False)
-    fwd = (time.perf_counter() - t0) / args.steps
+
+    def timed(grads):
+        for _ in range(args.warmup):
+            b.run(params, grads=grads)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = b.run(params, grads=grads)
+        return (time.perf_counter() - t0) / args.steps, out
+
+    # generic step kernels, then the run-time specialised ones (the faster
+    # form is the line's value; both are reported)
+    full_generic, _ = timed(True)
+    spec = {"generic_ms": full_generic * 1e3}
+    try:
+        t0 = time.perf_counter()
+        spec["programs"] = b.specialize()
+        spec["specialize_s"] = time.perf_counter() - t0
+        full_spec, _ = timed(True)
+        spec["specialized_ms"] = full_spec * 1e3
+        spec["used"] = "specialized" if full_spec < full_generic else "generic"
+        if full_spec >= full_generic:
+            b.compile()
+    except Exception as exc:   # no run-time compiler: generic kernels
+        spec["error"] = str(exc)[:200]
+        spec["used"] = "generic"
+    full, (e, g) = timed(True)
+    fwd, _ = timed(False)
     fwd_upd = st["logical_updates"]
     total = 3 * fwd_upd      # forward, then U^dagger on phi and on lambda
-    # algorithmic FP32 flops of one run: a single-qubit operator is a 2 x 2
-    # complex matrix on every amplitude (14 flops per amplitude: two complex
-    # products and a sum), CZ none; the adjoint sweep applies each operator
-    # to two states and forms Im conj(lambda) P phi (4 flops per amplitude:
-    # the gradient needs no real part) for every rotation; lambda = H psi
-    # costs 8 flops per amplitude and term
+    # algorithmic FP32 flops of one run, each operator at the fewest flops
+    # its form needs per amplitude: a rotation c 1 + i s P (P = X, Y, Z) 6
+    # (one product and one fused multiply-add per real component), a fixed
+    # 2 x 2 gate 14 (two complex products and a sum), CZ none; the adjoint
+    # sweep applies each operator to two states and forms Im conj(lambda) P phi
+    # for every rotation (4 per amplitude: four products summed, the gradient
+    # needing no real part); lambda = H psi costs 8 per amplitude and term
     flops = 0
     for p in probs:
         a = 1 << p["num_qubits"]
-        one_q = sum(1 for op in p["ops"] if op["op"] == "gadget" or not op.get("ctrls"))
         rot = sum(1 for op in p["ops"] if op["op"] == "gadget" and "param" in op)
-        flops += a * (14 * one_q + 2 * 14 * one_q + 4 * rot + 8 * len(p["coeffs"]))
+        fixed = sum(1 for op in p["ops"] if op["op"] == "unitary" and not op.get("ctrls"))
+        fixed += sum(1 for op in p["ops"] if op["op"] == "gadget" and "param" not in op)
+        flops += a * (3 * (6 * rot + 14 * fixed) + 4 * rot + 8 * len(p["coeffs"]))
     achieved = flops / full / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
@@ -586,7 +605,7 @@ def bench_batch(args, torch, qs, synth):
                       "launch_steps": st["num_steps"], "forward_only_ms": fwd * 1e3,
                       "forward_updates_per_s": fwd_upd / fwd, "gradients": int(params.size),
                       "circuits_per_s_with_gradient": st["num_circuits"] / full,
-                      "energy_mean": float(np.mean(e))})
+                      "step_kernels": spec, "energy_mean": float(np.mean(e))})
 
 
 def bench_sv34(args, torch, qs, synth):

@@ -509,6 +509,19 @@ int qs_batch_get_state(qs_batch *b, int circuit, double *re_im);
  * counts 2^N per operator of every circuit (one forward application). */
 int qs_batch_stats(const qs_batch *b, int *num_circuits, int *num_steps, uint64_t *total_amps,
                    uint64_t *logical_updates);
+/* Specialises the compiled batch's register-path steps (tiles of at least
+ * 2^9 amplitudes) at run time, as qs_circuit_specialize does for tile steps:
+ * a step's phases and operators become compile-time constants of generated
+ * kernels (one forward and one backward kernel per step index, switching
+ * over the distinct step programs; circuits of the same structure share
+ * theirs), compiled by $ROCM_PATH/llvm/bin/clang++ and loaded as modules;
+ * the graphs are captured again.  Results equal those of the generic
+ * kernels.  *num_programs (may be NULL) receives the number of distinct
+ * programs.  QS_E_PRECOND if the batch is not compiled or has more than 512
+ * programs (or 65536 operators in them): the generic kernels stay.  A
+ * failed compilation (QS_E_HIP) also leaves the generic kernels.  Compiling
+ * the batch again drops the specialisation. */
+int qs_batch_specialize(qs_batch *b, int *num_programs);
 
 #ifdef __cplusplus
 }

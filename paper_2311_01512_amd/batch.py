@@ -50,6 +50,13 @@ class Batch:
         self.compiled = True
         return self
 
+    def specialize(self):
+        """Run-time specialised step kernels (qs_batch_specialize); returns
+        the number of distinct step programs."""
+        if not self.compiled:
+            raise RuntimeError("compile the batch first")
+        return N.qs_batch_specialize(self._b)
+
     def run(self, params, grads=True):
         """params: concatenated parameter vectors.  Returns (energies, grads)."""
         return N.qs_batch_run(self._b, params, len(self.num_qubits), sum(self.num_params), grads)

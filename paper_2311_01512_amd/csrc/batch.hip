@@ -9,16 +9,17 @@
 // operators to the tile.  Operators are absorbed into a step only if they
 // commute with every operator left behind (no shared qubit), so the order of
 // the circuit is respected.  All circuits' s-th steps form one kernel launch.
-#include "common.hpp"
+#include "batch_dev.hpp"
+#include "circuit.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <map>
+#include <sstream>
+#include <string>
 
 namespace qs {
-
-constexpr int kTileMax = 12;
-
-enum { BOP_ROT = 0, BOP_GATE = 1, BOP_CZ = 2 };
 
 struct BOp {
     int kind, q0, q1, pauli, param;
@@ -43,95 +44,10 @@ struct BCirc {
     int param_off;
 };
 
-// Device descriptors.
-struct DOp {
-    int kind;
-    int pos0, pos1;   // positions of q0 / q1 inside the step's qubit set, -1 if outside
-    int q0, q1;
-    int pauli;
-    int param;        // global parameter index (rotations)
-    int grad;         // rotation slot, -1 for other operators
-    uint64_t gpart;   // first gradient partial of this rotation (one per tile)
-    int rbit;         // register bit of a 1-qubit operator in its phase (register path); for
-                      // a CZ, of q0, or -1 where q0 is not a register coordinate
-    int rbit1;        // a CZ's register bit of q1, or -1
-    int czrun;        // register path, CZ: bit 0 first, bit 1 last of a run of CZs in its phase
-    int slot;         // gradient slot of a rotation within its phase (register path)
-    double scale;
-    double m[8];      // fixed gate, row-major (re, im)
-};
-
-struct DStep {
-    uint64_t amp_off;
-    InsertPlan plan;  // zeros at the step's qubits: spreads the tile number
-    int qn;
-    int qpos[kTileMax];
-    int op_begin, op_end;
-    int ph_begin, ph_end;   // register phases (steps of >= kRegMinQubits qubits)
-};
-
-// Register phases of a step (tiles of at least 2^kRegMinQubits amplitudes):
-// thread t of the block holds the 8 tile coordinates tau(t) | rho(u), where
-// rho puts the bits of u on the coordinates rc[0..2] and tau deposits the
-// bits of t, in order, on the others (zeros inserted at lo).  Every 1-qubit
-// operator of the phase acts on one of the rc coordinates, so it only mixes
-// registers of one thread; CZ is diagonal and needs none.  The tile moves
-// through LDS once per phase change.
-constexpr int kRegMinQubits = 9;     // 64 threads: whole wavefronts
-constexpr int kPhaseRotMax = 32;     // gradient slots per phase
-struct BPhase {
-    uint32_t lo[3];                  // (1 << rc) - 1, ascending
-    int rc[3];                       // coordinate of register bit j
-    int op_begin, op_end;
-};
-
 struct DTerm {
     uint64_t x, yz;
     double cre, cim;  // h_n i^{#Y}
 };
-
-// v moved across lanes by a DPP control (both 32-bit halves); lanes of rows
-// outside row_mask receive 0.
-template <int CTRL, int ROW_MASK = 0xf>
-__device__ __forceinline__ double dpp_move(double v)
-{
-    int lo, hi;
-    __builtin_memcpy(&lo, &v, 4);
-    __builtin_memcpy(&hi, reinterpret_cast<const char *>(&v) + 4, 4);
-    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false);
-    double r;
-    __builtin_memcpy(&r, &lo, 4);
-    __builtin_memcpy(reinterpret_cast<char *>(&r) + 4, &hi, 4);
-    return r;
-}
-
-// Sum over the active lanes of the wavefront, returned to every lane, with
-// data-parallel primitive moves instead of LDS permutes: within each row of
-// 16 lanes by quad permutes and mirrors (every lane ends with its row's
-// sum), then across rows by the row broadcasts of lanes 15 and 31 (the last
-// lane ends with the total).  Moves from inactive lanes bring 0, so for the
-// active sets used here, a prefix of 2^k lanes, the last active lane holds
-// the total and is read back.
-__device__ __forceinline__ double bwave_sum(double v)
-{
-    v += dpp_move<0xB1>(v);        // quad_perm [1, 0, 3, 2]
-    v += dpp_move<0x4E>(v);        // quad_perm [2, 3, 0, 1]
-    v += dpp_move<0x141>(v);       // row_half_mirror
-    v += dpp_move<0x140>(v);       // row_mirror
-    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-    int lo, hi;
-    __builtin_memcpy(&lo, &v, 4);
-    __builtin_memcpy(&hi, reinterpret_cast<const char *>(&v) + 4, 4);
-    const int last = 63 - __builtin_clzll(__builtin_amdgcn_read_exec());
-    lo = __builtin_amdgcn_readlane(lo, last);
-    hi = __builtin_amdgcn_readlane(hi, last);
-    double r;
-    __builtin_memcpy(&r, &lo, 4);
-    __builtin_memcpy(reinterpret_cast<char *>(&r) + 4, &hi, 4);
-    return r;
-}
 
 // (re, im) summed over the block; valid in thread 0.
 __device__ void bblock_sum2(double &re, double &im, double *scratch)
@@ -161,32 +77,6 @@ __device__ __forceinline__ uint64_t tile_offset(int j, const DStep &st)
     uint64_t o = 0;
     for (int b = 0; b < st.qn; b++) o |= (uint64_t)((j >> b) & 1) << st.qpos[b];
     return o;
-}
-
-// 2 x 2 matrix of an operator; dir = -1 gives its adjoint.  A rotation's
-// cos and sin come from the per-operator table trig (filled by k_batch_trig
-// for the current parameters), not from a per-lane sincos.
-template <typename R>
-__device__ __forceinline__ void op_matrix(const DOp &op, const double *trig, int dir, C2<R> (&u)[4])
-{
-    if (op.kind == BOP_ROT) {
-        const double c = trig[0], s = dir * trig[1];
-        if (op.pauli == 1) {          // c 1 + i s X
-            u[0] = mk<R>(c, 0); u[1] = mk<R>(0, s); u[2] = mk<R>(0, s); u[3] = mk<R>(c, 0);
-        } else if (op.pauli == 2) {   // c 1 + i s Y
-            u[0] = mk<R>(c, 0); u[1] = mk<R>(s, 0); u[2] = mk<R>(-s, 0); u[3] = mk<R>(c, 0);
-        } else {                      // c 1 + i s Z
-            u[0] = mk<R>(c, s); u[1] = mk<R>(0, 0); u[2] = mk<R>(0, 0); u[3] = mk<R>(c, -s);
-        }
-    } else if (dir > 0) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) u[k] = mk<R>((R)op.m[2 * k], (R)op.m[2 * k + 1]);
-    } else {                          // conjugate transpose
-        u[0] = mk<R>((R)op.m[0], (R)-op.m[1]);
-        u[1] = mk<R>((R)op.m[4], (R)-op.m[5]);
-        u[2] = mk<R>((R)op.m[2], (R)-op.m[3]);
-        u[3] = mk<R>((R)op.m[6], (R)-op.m[7]);
-    }
 }
 
 // cos and sin of every rotation's angle scale * parameter, once per run.
@@ -370,198 +260,6 @@ __global__ __launch_bounds__(256) void k_batch_backward(C2<R> *__restrict__ amps
 
 // ---- register-phase path (tiles of >= 2^kRegMinQubits amplitudes) ----------------------
 
-__device__ __forceinline__ uint32_t bphase_tau(uint32_t t, const BPhase &ph)
-{
-#pragma unroll
-    for (int b = 0; b < 3; b++) {
-        const uint32_t lo = ph.lo[b];
-        t = (t & lo) | ((t & ~lo) << 1);
-    }
-    return t;
-}
-
-__device__ __forceinline__ uint32_t bphase_rho(int u, const BPhase &ph)
-{
-    return ((uint32_t)(u & 1) << ph.rc[0]) | ((uint32_t)((u >> 1) & 1) << ph.rc[1]) |
-           ((uint32_t)((u >> 2) & 1) << ph.rc[2]);
-}
-
-// 2 x 2 matrix (m0 m1; m2 m3) on the register pairs (u0, u0 | 1 << J).
-template <typename R, int J>
-__device__ __forceinline__ void reg_pairs(C2<R> (&x)[8], C2<R> m0, C2<R> m1, C2<R> m2, C2<R> m3)
-{
-#pragma unroll
-    for (int u0 = 0; u0 < 8; u0++) {
-        if ((u0 >> J) & 1) continue;
-        const C2<R> a = x[u0], b = x[u0 | (1 << J)];
-        C2<R> p = mk<R>(0, 0), q = mk<R>(0, 0);
-        cmac<R>(p, m0, a);
-        cmac<R>(p, m1, b);
-        cmac<R>(q, m2, a);
-        cmac<R>(q, m3, b);
-        x[u0] = p;
-        x[u0 | (1 << J)] = q;
-    }
-    // a distinct empty statement per J: keeps the compiler from sinking the
-    // three dispatch arms of reg_gate into one, which would address the
-    // registers through pointers (private memory)
-    if constexpr (J == 0) asm volatile("; reg pairs 0");
-    else if constexpr (J == 1) asm volatile("; reg pairs 1");
-    else asm volatile("; reg pairs 2");
-}
-
-// Partial of Im <lambda|P|phi> over the register pairs (u0, u0 | 1 << J) of a
-// rotation exp(i theta P) on register bit J.
-template <typename R, int J>
-__device__ __forceinline__ void reg_grad_pairs(const C2<R> (&x)[8], const C2<R> (&y)[8], int pauli, double &im)
-{
-#pragma unroll
-    for (int u0 = 0; u0 < 8; u0++) {
-        if ((u0 >> J) & 1) continue;
-        const int u1 = u0 | (1 << J);
-        const C2<R> f0 = x[u0], f1 = x[u1], l0 = y[u0], l1 = y[u1];
-        C2<R> p0, p1;   // (P phi) at the two members
-        if (pauli == 1) {
-            p0 = f1;
-            p1 = f0;
-        } else if (pauli == 2) {   // Y: -i phi_1 at member 0, +i phi_0 at member 1
-            p0 = mk<R>(f1.y, -f1.x);
-            p1 = mk<R>(-f0.y, f0.x);
-        } else {
-            p0 = f0;
-            p1 = mk<R>(-f1.x, -f1.y);
-        }
-        if constexpr (same_type<R, float>::value) {
-            // complex64 states: the pair's products in FP32 (relative error
-            // about 1e-7, below the states' own), the sums over lanes, waves
-            // and tiles in FP64
-            im += (double)(l0.x * p0.y - l0.y * p0.x + l1.x * p1.y - l1.y * p1.x);
-        } else {
-            im += (double)l0.x * p0.y - (double)l0.y * p0.x + (double)l1.x * p1.y - (double)l1.y * p1.x;
-        }
-    }
-    if constexpr (J == 0) asm volatile("; grad pairs 0");
-    else if constexpr (J == 1) asm volatile("; grad pairs 1");
-    else asm volatile("; grad pairs 2");
-}
-
-// Rotation c 1 + i s P (P = X, Y, Z by PA = 1, 2, 3) on the register pairs
-// (u0, u0 | 1 << J): the matrix's zeros and its real or imaginary entries
-// spelled out, 8 FP operations per pair instead of a general 2 x 2
-// complex product's 16.
-template <typename R, int J, int PA>
-__device__ __forceinline__ void reg_rot_pairs(C2<R> (&x)[8], R c, R s)
-{
-#pragma unroll
-    for (int u0 = 0; u0 < 8; u0++) {
-        if ((u0 >> J) & 1) continue;
-        const C2<R> a = x[u0], b = x[u0 | (1 << J)];
-        if constexpr (PA == 1) {          // (c a + i s b, i s a + c b)
-            x[u0] = mk<R>(c * a.x - s * b.y, c * a.y + s * b.x);
-            x[u0 | (1 << J)] = mk<R>(c * b.x - s * a.y, c * b.y + s * a.x);
-        } else if constexpr (PA == 2) {   // (c a + s b, c b - s a)
-            x[u0] = mk<R>(c * a.x + s * b.x, c * a.y + s * b.y);
-            x[u0 | (1 << J)] = mk<R>(c * b.x - s * a.x, c * b.y - s * a.y);
-        } else {                          // ((c + i s) a, (c - i s) b)
-            x[u0] = mk<R>(c * a.x - s * a.y, c * a.y + s * a.x);
-            x[u0 | (1 << J)] = mk<R>(c * b.x + s * b.y, c * b.y - s * b.x);
-        }
-    }
-    // distinct empty statements, as in reg_pairs
-    if constexpr (J == 0) asm volatile("; rot pairs 0");
-    else if constexpr (J == 1) asm volatile("; rot pairs 1");
-    else asm volatile("; rot pairs 2");
-}
-
-template <typename R, int PA>
-__device__ __forceinline__ void reg_rot_p(C2<R> (&x)[8], int rbit, R c, R s)
-{
-    switch (rbit) {
-    case 0: reg_rot_pairs<R, 0, PA>(x, c, s); break;
-    case 1: reg_rot_pairs<R, 1, PA>(x, c, s); break;
-    default: reg_rot_pairs<R, 2, PA>(x, c, s); break;
-    }
-}
-
-// A rotation exp(i theta P) (s = dir sin(theta)) on register bit rbit.
-template <typename R>
-__device__ __forceinline__ void reg_rot(C2<R> (&x)[8], int rbit, int pauli, R c, R s)
-{
-    if (pauli == 1) reg_rot_p<R, 1>(x, rbit, c, s);
-    else if (pauli == 2) reg_rot_p<R, 2>(x, rbit, c, s);
-    else reg_rot_p<R, 3>(x, rbit, c, s);
-}
-
-template <typename R>
-__device__ __forceinline__ void reg_gate(C2<R> (&x)[8], int rbit, const C2<R> (&u)[4])
-{
-    switch (rbit) {
-    case 0: reg_pairs<R, 0>(x, u[0], u[1], u[2], u[3]); break;
-    case 1: reg_pairs<R, 1>(x, u[0], u[1], u[2], u[3]); break;
-    default: reg_pairs<R, 2>(x, u[0], u[1], u[2], u[3]); break;
-    }
-}
-
-// CZ on the register path.  Which of a thread's 8 registers a CZ negates is
-// an 8-bit mask over u: a qubit held in register bit j selects the registers
-// with bit j of u set (0xAA, 0xCC, 0xF0), a qubit on a thread coordinate is 1
-// for all 8 registers or none, a qubit outside the tile reads the tile's base
-// bit; the CZ negates where both are 1.  CZs are diagonal and commute with
-// each other, so a run of them is one mask (the xor of theirs) and one pass
-// of sign flips.
-__device__ __forceinline__ uint32_t cz_side(int pos, int rb, int q, uint32_t tau, uint64_t base)
-{
-    if (rb >= 0) return rb == 0 ? 0xAAu : (rb == 1 ? 0xCCu : 0xF0u);
-    if (pos >= 0) return 0u - ((tau >> pos) & 1u);
-    return ((base >> q) & 1ULL) ? 0xFFu : 0u;
-}
-
-__device__ __forceinline__ uint32_t cz_mask(const DOp &op, uint32_t tau, uint64_t base)
-{
-    return cz_side(op.pos0, op.rbit, op.q0, tau, base) & cz_side(op.pos1, op.rbit1, op.q1, tau, base);
-}
-
-__device__ __forceinline__ float flip_sign(float v, uint32_t s) { return __uint_as_float(__float_as_uint(v) ^ s); }
-
-__device__ __forceinline__ double flip_sign(double v, uint32_t s)
-{
-    return __longlong_as_double(__double_as_longlong(v) ^ (long long)((uint64_t)s << 32));
-}
-
-// Negates register u where bit u of mask is set (the sign bit flipped).
-template <typename R>
-__device__ __forceinline__ void reg_sign(C2<R> (&x)[8], uint32_t mask)
-{
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-        const uint32_t s = (mask << (31 - u)) & 0x80000000u;
-        x[u] = mk<R>(flip_sign(x[u].x, s), flip_sign(x[u].y, s));
-    }
-}
-
-// Global offset of tile coordinates c (deposited at the step's qubits).
-__device__ __forceinline__ uint64_t tile_offset_bits(uint32_t c, const DStep &st)
-{
-    uint64_t o = 0;
-    for (int b = 0; b < st.qn; b++) o |= (uint64_t)((c >> b) & 1u) << st.qpos[b];
-    return o;
-}
-
-// Global offsets of the 8 registers of a phase: the qubits of rc[j] for the
-// bits j of u (no loops, so register indices stay compile-time).
-struct RegOffsets {
-    uint64_t q[3];
-    __device__ __forceinline__ RegOffsets(const BPhase &ph, const DStep &st)
-    {
-#pragma unroll
-        for (int j = 0; j < 3; j++) q[j] = 1ULL << st.qpos[ph.rc[j]];
-    }
-    __device__ __forceinline__ uint64_t operator()(int u) const
-    {
-        return ((u & 1) ? q[0] : 0ULL) | ((u & 2) ? q[1] : 0ULL) | ((u & 4) ? q[2] : 0ULL);
-    }
-};
-
 template <typename R>
 __global__ __launch_bounds__(512) void k_batch_forward_reg(C2<R> *__restrict__ amps, const DStep *__restrict__ steps,
                                                             const BPhase *__restrict__ phases,
@@ -587,39 +285,10 @@ __global__ __launch_bounds__(512) void k_batch_forward_reg(C2<R> *__restrict__ a
     }
     for (int p = st.ph_begin; p < st.ph_end; p++) {
         const BPhase &P = phases[p];
-        if (p > st.ph_begin) {
-            const BPhase &Q = phases[p - 1];
-            const uint32_t tn = bphase_tau(t, P);
-            __syncthreads();   // earlier reads of the LDS tile are done
-            if (active) {
-#pragma unroll
-                for (int u = 0; u < 8; u++) v[tau | bphase_rho(u, Q)] = x[u];
-            }
-            __syncthreads();
-            if (active) {
-#pragma unroll
-                for (int u = 0; u < 8; u++) x[u] = v[tn | bphase_rho(u, P)];
-            }
-            tau = tn;
-        }
+        if (p > st.ph_begin) tau = bphase_exchange<R>(x, v, tau, phases[p - 1], P, active);
         if (!active) continue;
         uint32_t czm = 0;   // sign mask of the current run of CZs
-        for (int k = P.op_begin; k < P.op_end; k++) {
-            const DOp &op = ops[k];
-            if (op.kind == BOP_CZ) {
-                czm ^= cz_mask(op, tau, base);
-                if (op.czrun & 2) {   // the run's last CZ
-                    reg_sign<R>(x, czm);
-                    czm = 0;
-                }
-            } else if (op.kind == BOP_ROT) {
-                reg_rot<R>(x, op.rbit, op.pauli, (R)trig[2 * k], (R)trig[2 * k + 1]);
-            } else {
-                C2<R> u[4];
-                op_matrix<R>(op, trig + 2 * k, +1, u);
-                reg_gate<R>(x, op.rbit, u);
-            }
-        }
+        for (int k = P.op_begin; k < P.op_end; k++) fwd_op<R>(x, ops[k], k, trig, tau, base, czm);
     }
     if (active) {
         const uint64_t xo = base | tile_offset_bits(tau, st);
@@ -632,8 +301,10 @@ __global__ __launch_bounds__(512) void k_batch_forward_reg(C2<R> *__restrict__ a
 // Adjoint sweep on registers: phases and operators last first; a rotation's
 // partial Im <lambda|P|phi> comes from the register pairs it couples, before
 // U^dagger is applied to both states.  Each wavefront leaves its partial in
-// the rotation's LDS slot; thread 0 adds the wavefronts' partials (fixed
-// order) after the next barrier.
+// the rotation's LDS slot; after the barrier that opens the next exchange
+// one thread per rotation adds the wavefronts' partials (fixed order), and
+// those reads complete before the exchange's second barrier, after which
+// the next phase writes the slots again.
 template <typename R>
 __global__ __launch_bounds__(512) void k_batch_backward_reg(C2<R> *__restrict__ amps, uint64_t lambda_base,
                                                              const DStep *__restrict__ steps,
@@ -670,87 +341,20 @@ __global__ __launch_bounds__(512) void k_batch_backward_reg(C2<R> *__restrict__ 
             y[u] = l[o];
         }
     }
-    int pend_phase = -1;   // phase whose rotation partials sit in red
-    // the finished phase's partials summed over the waves, one thread per
-    // operator (the reads complete before the barrier that
-    // precedes the next writes to red)
-    auto flush = [&]() {
-        if (pend_phase >= 0) {
-            const BPhase &D = phases[pend_phase];
-            for (int i = (int)t; i < D.op_end - D.op_begin; i += (int)blockDim.x) {
-                const DOp &op = ops[D.op_begin + i];
-                if (op.grad < 0) continue;
-                double v = 0.0;
-                for (int v2 = 0; v2 < nwaves; v2++) v += red[op.slot][v2];
-                gpart[op.gpart + w.y] = v;
-            }
-        }
-        pend_phase = -1;
-    };
     for (int p = st.ph_end - 1; p >= st.ph_begin; p--) {
         const BPhase &P = phases[p];
         if (p < st.ph_end - 1) {
-            const BPhase &Q = phases[p + 1];
-            const uint32_t tn = bphase_tau(t, P);
+            const BPhase &D = phases[p + 1];   // the finished phase
             __syncthreads();   // earlier LDS reads done; the finished phase's partials visible
-            flush();
-            if (active) {
-#pragma unroll
-                for (int u = 0; u < 8; u++) {
-                    const uint32_t c = tau | bphase_rho(u, Q);
-                    vphi[c] = x[u];
-                    vlam[c] = y[u];
-                }
-            }
-            __syncthreads();
-            if (active) {
-#pragma unroll
-                for (int u = 0; u < 8; u++) {
-                    const uint32_t c = tn | bphase_rho(u, P);
-                    x[u] = vphi[c];
-                    y[u] = vlam[c];
-                }
-            }
-            tau = tn;
+            flush_phase(ops, D.op_begin, D.op_end, red, nwaves, w.y, gpart);
+            tau = bphase_exchange2<R>(x, y, vphi, vlam, tau, D, P, active);
         }
         if (!active) continue;
         uint32_t czm = 0;   // sign mask of the current run of CZs
-        for (int k = P.op_end - 1; k >= P.op_begin; k--) {
-            const DOp &op = ops[k];
-            if (op.kind == BOP_CZ) {
-                czm ^= cz_mask(op, tau, base);
-                if (op.czrun & 1) {   // the run's first CZ, reached last
-                    reg_sign<R>(x, czm);
-                    reg_sign<R>(y, czm);
-                    czm = 0;
-                }
-                continue;
-            }
-            C2<R> u[4];
-            op_matrix<R>(op, trig + 2 * k, -1, u);
-            if (op.grad >= 0) {
-                double im = 0.0;
-                switch (op.rbit) {
-                case 0: reg_grad_pairs<R, 0>(x, y, op.pauli, im); break;
-                case 1: reg_grad_pairs<R, 1>(x, y, op.pauli, im); break;
-                default: reg_grad_pairs<R, 2>(x, y, op.pauli, im); break;
-                }
-                im = bwave_sum(im);
-                if (lane == 0) red[op.slot][wave] = im;
-            }
-            if (op.kind == BOP_ROT) {
-                const R c = (R)trig[2 * k], sn = -(R)trig[2 * k + 1];   // the adjoint
-                reg_rot<R>(x, op.rbit, op.pauli, c, sn);
-                reg_rot<R>(y, op.rbit, op.pauli, c, sn);
-            } else {
-                reg_gate<R>(x, op.rbit, u);
-                reg_gate<R>(y, op.rbit, u);
-            }
-        }
-        pend_phase = p;
+        for (int k = P.op_end - 1; k >= P.op_begin; k--) bwd_op<R>(x, y, ops[k], k, trig, tau, base, czm, red, lane, wave);
     }
     __syncthreads();
-    flush();
+    flush_phase(ops, phases[st.ph_begin].op_begin, phases[st.ph_begin].op_end, red, nwaves, w.y, gpart);
     if (active) {
         const uint64_t xo = base | tile_offset_bits(tau, st);
         const RegOffsets ro(phases[st.ph_begin], st);
@@ -885,6 +489,15 @@ struct qs_batch {
     hipGraphExec_t g_fwd = nullptr, g_full = nullptr;
     hipGraph_t gr_fwd = nullptr, gr_full = nullptr;
     bool last_run_had_grads = false;
+    // host copies of the device tables, for run-time specialisation
+    std::vector<DStep> h_steps;
+    std::vector<DOp> h_ops;
+    std::vector<BPhase> h_phases;
+    std::vector<int> step_launch;    // launch index (step s of its circuit) of every step
+    // specialised register-path kernels per launch index (null: the generic ones)
+    std::vector<void *> jit_modules;
+    std::vector<void *> jit_fwd, jit_bwd;
+    int num_programs = 0;
 };
 
 namespace qs {
@@ -969,7 +582,13 @@ static int launch_phase_kernels(qs_batch *b, bool grads)
                                    (const uint2 *)b->d_work[p], (const double *)b->d_trig);
             QS_LAUNCH_CHECK();
         }
-        if (b->phase_blocks_reg[p] > 0) {
+        if (b->phase_blocks_reg[p] > 0 && p < (int)b->jit_fwd.size() && b->jit_fwd[p]) {
+            void *amps = b->amps;
+            const void *steps = b->d_steps, *work = b->d_work_reg[p], *trig = b->d_trig;
+            void *args[] = {&amps, &steps, &work, &trig};
+            QS_HIP(hipModuleLaunchKernel((hipFunction_t)b->jit_fwd[p], b->phase_blocks_reg[p], 1, 1, rblock, 1, 1,
+                                         (unsigned)lds1, b->stream, args, nullptr));
+        } else if (b->phase_blocks_reg[p] > 0) {
             if (b->precision == QS_C64)
                 hipLaunchKernelGGL(k_batch_forward_reg<float>, dim3(b->phase_blocks_reg[p]), dim3(rblock), lds1,
                                    b->stream, (float2 *)b->amps, (const DStep *)b->d_steps,
@@ -1011,7 +630,14 @@ static int launch_phase_kernels(qs_batch *b, bool grads)
                                    b->d_gpart);
             QS_LAUNCH_CHECK();
         }
-        if (b->phase_blocks_reg[p] > 0) {
+        if (b->phase_blocks_reg[p] > 0 && p < (int)b->jit_bwd.size() && b->jit_bwd[p]) {
+            void *amps = b->amps, *gpart = b->d_gpart;
+            unsigned long long lambda_base = b->total_amps;
+            const void *steps = b->d_steps, *ops = b->d_ops, *work = b->d_work_reg[p], *trig = b->d_trig;
+            void *args[] = {&amps, &lambda_base, &steps, &ops, &work, &trig, &gpart};
+            QS_HIP(hipModuleLaunchKernel((hipFunction_t)b->jit_bwd[p], b->phase_blocks_reg[p], 1, 1, rblock, 1, 1,
+                                         (unsigned)(2 * lds1), b->stream, args, nullptr));
+        } else if (b->phase_blocks_reg[p] > 0) {
             if (b->precision == QS_C64)
                 hipLaunchKernelGGL(k_batch_backward_reg<float>, dim3(b->phase_blocks_reg[p]), dim3(rblock),
                                    2 * lds1, b->stream, (float2 *)b->amps, b->total_amps,
@@ -1058,6 +684,17 @@ static int upload(P **dst, const void *src, size_t bytes)
     return QS_OK;
 }
 
+// Unloads the specialised step kernels (the caller has waited for the
+// batch's stream).
+static void release_jit(qs_batch *b)
+{
+    for (void *m : b->jit_modules) (void)hipModuleUnload((hipModule_t)m);
+    b->jit_modules.clear();
+    b->jit_fwd.clear();
+    b->jit_bwd.clear();
+    b->num_programs = 0;
+}
+
 static void release(qs_batch *b)
 {
     auto f = [](void *p) {
@@ -1072,6 +709,7 @@ static void release(qs_batch *b)
     if (b->gr_full) (void)hipGraphDestroy(b->gr_full);
     b->g_fwd = b->g_full = nullptr;
     b->gr_fwd = b->gr_full = nullptr;
+    release_jit(b);   // after the graphs that launch its kernels
     f(b->amps);
     f(b->d_steps);
     f(b->d_ops);
@@ -1116,6 +754,291 @@ static void release(qs_batch *b)
     b->d_params = b->h_params = nullptr;
     b->d_trig = nullptr;
     b->compiled = false;
+}
+
+// ---- run-time specialised register-path steps --------------------------------------
+//
+// A register-path step is a program: its tile size, phases and operators.
+// Circuits of the same structure (the same qubit count and gate layout, any
+// parameters) share their programs.  For every launch index s, one forward
+// and one backward kernel switch over the programs of the s-th steps; each
+// program is the generic kernel's code with its phases and operators as
+// compile-time records (batch_dev.hpp), so operator dispatch, operator-field
+// loads and the register copies where the dispatch arms meet disappear.
+// Angles stay run-time values (the trig table), as do the step's placement
+// (its DStep) and the gradient partials' addresses.
+
+constexpr int kMaxPrograms = 512;
+constexpr size_t kMaxProgramOps = 1u << 16;   // operator records over all programs
+
+static std::string jit_hexd(double v)
+{
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%a", v);
+    return buf;
+}
+
+// The fields of an operator that its register-path code reads.
+static std::string dop_init(const DOp &o)
+{
+    std::ostringstream s;
+    const bool cz = o.kind == BOP_CZ, rot = o.kind == BOP_ROT, gate = o.kind == BOP_GATE;
+    s << "{" << o.kind << ", " << o.pos0 << ", " << o.pos1 << ", " << (cz ? o.q0 : 0) << ", " << (cz ? o.q1 : 0)
+      << ", " << (rot ? o.pauli : 0) << ", 0, " << (o.grad >= 0 ? 0 : -1) << ", 0ull, " << o.rbit << ", " << o.rbit1
+      << ", " << (cz ? o.czrun : 0) << ", " << (o.grad >= 0 ? o.slot : 0) << ", 0.0, {";
+    for (int i = 0; i < 8; i++) s << (i ? ", " : "") << (gate ? jit_hexd(o.m[i]) : std::string("0.0"));
+    s << "}}";
+    return s.str();
+}
+
+static bool phase_has_grads(const qs_batch *b, const BPhase &P)
+{
+    for (int k = P.op_begin; k < P.op_end; k++)
+        if (b->h_ops[k].grad >= 0) return true;
+    return false;
+}
+
+// Program key of register-path step si: everything its generated code
+// depends on.
+static std::string program_key(const qs_batch *b, int si)
+{
+    const DStep &st = b->h_steps[si];
+    std::ostringstream k;
+    k << st.qn << ";";
+    for (int p = st.ph_begin; p < st.ph_end; p++) {
+        const BPhase &P = b->h_phases[p];
+        k << "P" << P.lo[0] << "," << P.lo[1] << "," << P.lo[2] << "," << P.rc[0] << "," << P.rc[1] << ","
+          << P.rc[2] << "," << P.op_begin - st.op_begin << "," << P.op_end - st.op_begin << ";";
+        for (int j = P.op_begin; j < P.op_end; j++) k << dop_init(b->h_ops[j]) << ";";
+    }
+    return k.str();
+}
+
+static void program_source(std::ostringstream &o, const qs_batch *b, int id, int si, bool bwd)
+{
+    const DStep &st = b->h_steps[si];
+    const int np = st.ph_end - st.ph_begin;
+    const unsigned nthr = 1u << (st.qn - 3);
+    std::ostringstream ph;
+    for (int k = 0; k < np; k++) {
+        const BPhase &P = b->h_phases[st.ph_begin + k];
+        ph << "    constexpr qs::BPhase P" << k << " = {{" << P.lo[0] << "u, " << P.lo[1] << "u, " << P.lo[2]
+           << "u}, {" << P.rc[0] << ", " << P.rc[1] << ", " << P.rc[2] << "}, " << P.op_begin - st.op_begin << ", "
+           << P.op_end - st.op_begin << "};\n";
+    }
+    auto op_line = [&](int j, const char *call) {
+        o << "        { constexpr qs::DOp O = " << dop_init(b->h_ops[j]) << "; " << call << "(x, "
+          << (bwd ? "y, " : "") << "O, st.op_begin + " << j - st.op_begin << ", trig, tau, base, czm"
+          << (bwd ? ", red, lane, wave" : "") << "); }\n";
+    };
+    if (!bwd) {
+        o << "template <typename R>\n__device__ __forceinline__ void bfwd_" << id
+          << "(qs::C2<R> *__restrict__ amps, const qs::DStep &st, uint64_t base, const double *__restrict__ trig, "
+             "unsigned char *lds)\n{\n"
+          << ph.str();
+        o << "    qs::C2<R> *v = reinterpret_cast<qs::C2<R> *>(lds);\n    qs::C2<R> *a = amps + st.amp_off;\n";
+        o << "    const bool active = threadIdx.x < " << nthr << "u;\n";
+        o << "    uint32_t tau = qs::bphase_tau(threadIdx.x, P0);\n    qs::C2<R> x[8];\n";
+        o << "    if (active) {\n        const uint64_t xo = base | qs::tile_offset_bits(tau, st);\n"
+             "        const qs::RegOffsets ro(P0, st);\n#pragma unroll\n"
+             "        for (int u = 0; u < 8; u++) x[u] = a[xo | ro(u)];\n    }\n";
+        for (int k = 0; k < np; k++) {
+            const BPhase &P = b->h_phases[st.ph_begin + k];
+            if (k) o << "    tau = qs::bphase_exchange<R>(x, v, tau, P" << k - 1 << ", P" << k << ", active);\n";
+            o << "    if (active) {\n        uint32_t czm = 0;\n";
+            for (int j = P.op_begin; j < P.op_end; j++) op_line(j, "qs::fwd_op<R>");
+            o << "        (void)czm;\n    }\n";
+        }
+        o << "    if (active) {\n        const uint64_t xo = base | qs::tile_offset_bits(tau, st);\n"
+             "        const qs::RegOffsets ro(P"
+          << np - 1 << ", st);\n#pragma unroll\n        for (int u = 0; u < 8; u++) a[xo | ro(u)] = x[u];\n    }\n}\n\n";
+        return;
+    }
+    o << "template <typename R>\n__device__ __forceinline__ void bbwd_" << id
+      << "(qs::C2<R> *__restrict__ amps, uint64_t lambda_base, const qs::DStep &st, uint32_t tile, uint64_t base, "
+         "const qs::DOp *__restrict__ ops, const double *__restrict__ trig, double *__restrict__ gpart, "
+         "unsigned char *lds, double (*red)[8])\n{\n"
+      << ph.str();
+    o << "    qs::C2<R> *vphi = reinterpret_cast<qs::C2<R> *>(lds);\n    qs::C2<R> *vlam = vphi + " << (1u << st.qn)
+      << ";\n    qs::C2<R> *a = amps + st.amp_off;\n    qs::C2<R> *l = amps + lambda_base + st.amp_off;\n";
+    o << "    const uint32_t t = threadIdx.x;\n    const bool active = t < " << nthr
+      << "u;\n    const int lane = t & 63, wave = t >> 6;\n";
+    o << "    uint32_t tau = qs::bphase_tau(t, P" << np - 1 << ");\n    qs::C2<R> x[8], y[8];\n";
+    o << "    if (active) {\n        const uint64_t xo = base | qs::tile_offset_bits(tau, st);\n"
+         "        const qs::RegOffsets ro(P"
+      << np - 1
+      << ", st);\n#pragma unroll\n        for (int u = 0; u < 8; u++) {\n            const uint64_t o = xo | ro(u);\n"
+         "            x[u] = a[o];\n            y[u] = l[o];\n        }\n    }\n";
+    auto flush = [&](int k) {
+        const BPhase &D = b->h_phases[st.ph_begin + k];
+        if (phase_has_grads(b, D))
+            o << "    qs::flush_phase(ops, st.op_begin + " << D.op_begin - st.op_begin << ", st.op_begin + "
+              << D.op_end - st.op_begin << ", red, " << (nthr >> 6) << ", tile, gpart);\n";
+    };
+    for (int k = np - 1; k >= 0; k--) {
+        const BPhase &P = b->h_phases[st.ph_begin + k];
+        if (k < np - 1) {
+            o << "    __syncthreads();\n";
+            flush(k + 1);
+            o << "    tau = qs::bphase_exchange2<R>(x, y, vphi, vlam, tau, P" << k + 1 << ", P" << k << ", active);\n";
+        }
+        o << "    if (active) {\n        uint32_t czm = 0;\n";
+        for (int j = P.op_end - 1; j >= P.op_begin; j--) op_line(j, "qs::bwd_op<R>");
+        o << "        (void)czm;\n    }\n";
+    }
+    o << "    __syncthreads();\n";
+    flush(0);
+    o << "    if (active) {\n        const uint64_t xo = base | qs::tile_offset_bits(tau, st);\n"
+         "        const qs::RegOffsets ro(P0, st);\n#pragma unroll\n        for (int u = 0; u < 8; u++) {\n"
+         "            const uint64_t o = xo | ro(u);\n            a[o] = x[u];\n            l[o] = y[u];\n"
+         "        }\n    }\n}\n\n";
+}
+
+// Source of the forward (bwd = false) or backward kernel of launch index s:
+// the programs `progs` (id, representative step) and a switch over them.
+static std::string launch_source(const qs_batch *b, int s, const std::vector<std::pair<int, int>> &progs, bool bwd)
+{
+    const bool f32 = b->precision == QS_C64;
+    const char *c2 = f32 ? "float2" : "double2";
+    std::ostringstream o;
+    o << "#include \"batch_dev.hpp\"\n\n";
+    for (const auto &pr : progs) program_source(o, b, pr.first, pr.second, bwd);
+    if (!bwd) {
+        o << "extern \"C\" __global__ __launch_bounds__(512) void qs_bfwd_" << s << "(" << c2
+          << " *__restrict__ amps, const qs::DStep *__restrict__ steps, const uint2 *__restrict__ work, "
+             "const double *__restrict__ trig)\n{\n";
+    } else {
+        o << "extern \"C\" __global__ __launch_bounds__(512) void qs_bbwd_" << s << "(" << c2
+          << " *__restrict__ amps, unsigned long long lambda_base, const qs::DStep *__restrict__ steps, "
+             "const qs::DOp *__restrict__ ops, const uint2 *__restrict__ work, const double *__restrict__ trig, "
+             "double *__restrict__ gpart)\n{\n    __shared__ double red[qs::kPhaseRotMax][8];\n";
+    }
+    o << "    using R = " << (f32 ? "float" : "double") << ";\n    extern __shared__ unsigned char lds_raw[];\n";
+    o << "    const uint2 w = work[blockIdx.x];\n    const qs::DStep &st = steps[w.x];\n"
+         "    const uint64_t base = qs::insert_zeros(w.y, st.plan);\n    switch (st.prog) {\n";
+    for (const auto &pr : progs) {
+        if (!bwd)
+            o << "    case " << pr.first << ": bfwd_" << pr.first << "<R>(amps, st, base, trig, lds_raw); break;\n";
+        else
+            o << "    case " << pr.first << ": bbwd_" << pr.first
+              << "<R>(amps, lambda_base, st, w.y, base, ops, trig, gpart, lds_raw, red); break;\n";
+    }
+    o << "    default: break;\n    }\n}\n";
+    return o.str();
+}
+
+static int specialize_batch(qs_batch *b, int *num_programs)
+{
+    // programs of the register-path steps
+    std::map<std::string, int> ids;
+    std::vector<int> prog_of(b->h_steps.size(), -1);
+    std::vector<int> rep;   // representative step of every program
+    size_t total_ops = 0;
+    int launches = 0;
+    for (size_t si = 0; si < b->h_steps.size(); si++) {
+        const DStep &st = b->h_steps[si];
+        if (st.qn < kRegMinQubits) continue;
+        const std::string key = program_key(b, (int)si);
+        auto it = ids.find(key);
+        if (it == ids.end()) {
+            it = ids.emplace(key, (int)rep.size()).first;
+            rep.push_back((int)si);
+            total_ops += (size_t)(st.op_end - st.op_begin);
+        }
+        prog_of[si] = it->second;
+        launches = std::max(launches, b->step_launch[si] + 1);
+    }
+    if (num_programs) *num_programs = (int)rep.size();
+    if (rep.empty()) return QS_OK;
+    if ((int)rep.size() > kMaxPrograms || total_ops > kMaxProgramOps)
+        return fail(QS_E_PRECOND, "too many distinct step programs to specialise (" + std::to_string(rep.size()) +
+                                      " programs, " + std::to_string(total_ops) + " operators)");
+    // per launch index, the programs its steps use
+    std::vector<std::vector<std::pair<int, int>>> per_launch(launches);
+    {
+        std::vector<std::vector<char>> seen(launches, std::vector<char>(rep.size(), 0));
+        for (size_t si = 0; si < b->h_steps.size(); si++) {
+            const int pg = prog_of[si];
+            if (pg < 0) continue;
+            const int s = b->step_launch[si];
+            if (!seen[s][pg]) {
+                seen[s][pg] = 1;
+                per_launch[s].push_back({pg, rep[pg]});
+            }
+        }
+    }
+    std::vector<std::string> srcs;
+    std::vector<std::pair<int, bool>> src_of;   // (launch, backward)
+    for (int s = 0; s < launches; s++) {
+        if (per_launch[s].empty()) continue;
+        for (bool bwd : {false, true}) {
+            srcs.push_back(launch_source(b, s, per_launch[s], bwd));
+            src_of.push_back({s, bwd});
+        }
+    }
+    int dev = 0;
+    QS_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    QS_HIP(hipGetDeviceProperties(&prop, dev));
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    std::vector<std::vector<char>> codes;
+    int rc = compile_device_sources(srcs, arch, codes);
+    if (rc != QS_OK) return rc;
+
+    // the graphs hold the kernels they were captured with: both go, and the
+    // graphs are captured again with whichever kernels remain
+    QS_HIP(hipStreamSynchronize(b->stream));
+    if (b->g_fwd) (void)hipGraphExecDestroy(b->g_fwd);
+    if (b->g_full) (void)hipGraphExecDestroy(b->g_full);
+    if (b->gr_fwd) (void)hipGraphDestroy(b->gr_fwd);
+    if (b->gr_full) (void)hipGraphDestroy(b->gr_full);
+    b->g_fwd = b->g_full = nullptr;
+    b->gr_fwd = b->gr_full = nullptr;
+    release_jit(b);
+    auto recapture = [&]() {
+        int r = QS_OK;
+        if (b->use_graph && (r = capture(b, false, &b->gr_fwd, &b->g_fwd)) == QS_OK)
+            r = capture(b, true, &b->gr_full, &b->g_full);
+        if (r != QS_OK) b->compiled = false;
+        return r;
+    };
+    auto give_up = [&](const std::string &msg) {
+        const std::string m = msg;   // the generic kernels again
+        release_jit(b);
+        recapture();
+        return fail(QS_E_HIP, m);
+    };
+    std::vector<void *> fwd(launches, nullptr), bwd_k(launches, nullptr);
+    for (size_t k = 0; k < codes.size(); k++) {
+        hipModule_t mod;
+        if (hipModuleLoadData(&mod, codes[k].data()) != hipSuccess) {
+            (void)hipGetLastError();
+            return give_up("loading the specialised batch steps failed");
+        }
+        b->jit_modules.push_back(mod);
+        const int s = src_of[k].first;
+        const bool bwd = src_of[k].second;
+        const std::string name = (bwd ? "qs_bbwd_" : "qs_bfwd_") + std::to_string(s);
+        hipFunction_t f = nullptr;
+        if (hipModuleGetFunction(&f, mod, name.c_str()) != hipSuccess) {
+            (void)hipGetLastError();
+            return give_up("specialised kernel " + name + " missing from its module");
+        }
+        (bwd ? bwd_k : fwd)[s] = (void *)f;
+    }
+    // the steps' program numbers
+    for (size_t si = 0; si < b->h_steps.size(); si++) b->h_steps[si].prog = prog_of[si];
+    if (hipMemcpy(b->d_steps, b->h_steps.data(), b->h_steps.size() * sizeof(DStep), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return give_up("uploading the step table failed");
+    }
+    b->jit_fwd = fwd;
+    b->jit_bwd = bwd_k;
+    b->num_programs = (int)rep.size();
+    return recapture();
 }
 
 }  // namespace qs
@@ -1378,6 +1301,7 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
     std::vector<DStep> steps;
     std::vector<DOp> ops;
     std::vector<BPhase> phases;
+    b->step_launch.clear();
     std::vector<uint64_t> gfirst{0};
     b->rot_param.clear();
     b->rot_scale.clear();
@@ -1386,6 +1310,7 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
         BCirc &c = b->circs[ci];
         for (auto &s : c.steps) {
             DStep d{};
+            d.prog = -1;
             d.amp_off = c.amp_off;
             std::vector<int> qs_;
             for (int q = 0; q < c.n; q++)
@@ -1515,6 +1440,7 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
                 d.ph_end = (int)phases.size();
             }
             step_index[ci].push_back((int)steps.size());
+            b->step_launch.push_back((int)step_index[ci].size() - 1);
             steps.push_back(d);
         }
     }
@@ -1601,6 +1527,9 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
         b->phase_blocks_reg.push_back((unsigned)w.size());
     }
     up(&b->d_phases, phases);
+    b->h_steps = steps;
+    b->h_ops = ops;
+    b->h_phases = phases;
     if (rc != QS_OK) return rc;
     if ((rc = upload(&b->d_epart, nullptr, sizeof(double) * 2 * bm_circ.size())) != QS_OK) return rc;
     if ((rc = upload(&b->d_energy, nullptr, sizeof(double) * 2 * b->circs.size())) != QS_OK) return rc;
@@ -1691,6 +1620,13 @@ int qs_batch_stats(const qs_batch *b, int *num_circuits, int *num_steps, uint64_
     if (total_amps) *total_amps = amps;
     if (logical_updates) *logical_updates = upd;
     return QS_OK;
+}
+
+int qs_batch_specialize(qs_batch *b, int *num_programs)
+{
+    if (!b) return fail(QS_E_ARG, "null batch");
+    if (!b->compiled) return fail(QS_E_PRECOND, "batch is not compiled");
+    return specialize_batch(b, num_programs);
 }
 
 }  // extern "C"

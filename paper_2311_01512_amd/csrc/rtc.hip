@@ -1,6 +1,6 @@
-// Run-time compilation of device code for the specialised tile steps: HIP
-// source -> code object for the current GPU, by the ROCm clang run as child
-// processes, with a process cache and an on-disk cache.  (hiprtc is not
+// Run-time compilation of device code for the specialised tile steps and
+// batch steps: HIP source -> code object for the current GPU, by the ROCm
+// clang run as child processes, with a process cache and an on-disk cache.  (hiprtc is not
 // used: in a process that has loaded PyTorch it resolves to the compiler
 // bundled with PyTorch, whose code for these kernels spills to scratch
 // memory.)
@@ -25,8 +25,9 @@
 #include <string>
 #include <vector>
 
-// kRtcHeaderNames / kRtcHeaderSources: dev_core.hpp and tile_dev.hpp as
-// strings (written by the build from the sources in this directory)
+// kRtcHeaderNames / kRtcHeaderSources: dev_core.hpp, tile_dev.hpp and
+// batch_dev.hpp as strings (written by the build from the sources in this
+// directory)
 #include "qs_rtc_headers.inc"
 
 extern char **environ;
@@ -201,7 +202,7 @@ int compile_device_sources(const std::vector<std::string> &srcs, const std::stri
                 std::vector<char> log;
                 read_file(base + ".log", log);
                 if (err.empty())
-                    err = "run-time compilation of tile steps failed: " +
+                    err = "run-time compilation failed: " +
                           std::string(log.begin(), log.end()).substr(0, 2000);
             } else if (!cdir.empty()) {
                 cache_store(cache_path(cdir, keys[k]), keys[k], codes[k]);

@@ -106,6 +106,7 @@ _SIGS = {
     "qs_batch_run": [_P, _P, _P, _P],
     "qs_batch_get_state": [_P, _I, _P],
     "qs_batch_stats": [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
+    "qs_batch_specialize": [_P, C.POINTER(C.c_int)],
 }
 
 for _name, _args in _SIGS.items():
@@ -527,6 +528,12 @@ def qs_batch_get_state(b, circuit, num_qubits):
     a = np.empty(1 << num_qubits, dtype=np.complex128)
     check(lib.qs_batch_get_state(b, circuit, ptr(a)), "qs_batch_get_state")
     return a
+
+
+def qs_batch_specialize(b):
+    n = C.c_int(0)
+    check(lib.qs_batch_specialize(b, C.byref(n)), "qs_batch_specialize")
+    return n.value
 
 
 def qs_batch_stats(b):
