@@ -38,13 +38,25 @@ __global__ __launch_bounds__(256) void k_apply_pauli_sum(C2<R> *__restrict__ out
             re = o.x;
             im = o.y;
         }
-        for (int k = 0; k < t.count; k++) {
-            const uint64_t j = i ^ t.x[k];
-            const C2<R> v = in[j];
-            const double s = (__popcll(j & t.yz[k]) & 1) ? -1.0 : 1.0;
-            const double cr = s * t.cre[k], ci = s * t.cim[k];
-            re += cr * (double)v.x - ci * (double)v.y;
-            im += cr * (double)v.y + ci * (double)v.x;
+        // eight terms' gathers in flight before their sums (same order of
+        // additions as one term at a time)
+        constexpr int G = 8;
+        for (int k0 = 0; k0 < t.count; k0 += G) {
+            C2<R> vs[G];
+#pragma unroll
+            for (int u = 0; u < G; u++)
+                if (k0 + u < t.count) vs[u] = in[i ^ t.x[k0 + u]];
+#pragma unroll
+            for (int u = 0; u < G; u++) {
+                if (k0 + u >= t.count) break;
+                const int k = k0 + u;
+                const uint64_t j = i ^ t.x[k];
+                const C2<R> v = vs[u];
+                const double s = (__popcll(j & t.yz[k]) & 1) ? -1.0 : 1.0;
+                const double cr = s * t.cre[k], ci = s * t.cim[k];
+                re += cr * (double)v.x - ci * (double)v.y;
+                im += cr * (double)v.y + ci * (double)v.x;
+            }
         }
         out[i] = mk<R>((R)re, (R)im);
     }

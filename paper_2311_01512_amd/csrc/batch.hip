@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_batch_forward(C2<R> *__restrict__ amps,
     const uint64_t base = insert_zeros(w.y, st.plan);
     C2<R> *a = amps + st.amp_off;
     const int T = 1 << st.qn;
-    for (int j = threadIdx.x; j < T; j += blockDim.x) v[j] = a[base | tile_offset(j, st)];
+    for (int j = threadIdx.x; j < T; j += blockDim.x) v[j] = load_amp<R>(a, base | tile_offset(j, st), st.first);
     __syncthreads();
     for (int k = st.op_begin; k < st.op_end; k++) {
         tile_apply<R>(v, st.qn, ops[k], base, trig + 2 * k, +1);
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(512) void k_batch_forward_reg(C2<R> *__restrict__ a
         const uint64_t xo = base | tile_offset_bits(tau, st);
         const RegOffsets ro(f, st);
 #pragma unroll
-        for (int u = 0; u < 8; u++) x[u] = a[xo | ro(u)];
+        for (int u = 0; u < 8; u++) x[u] = load_amp<R>(a, xo | ro(u), st.first);
     }
     for (int p = st.ph_begin; p < st.ph_end; p++) {
         const BPhase &P = phases[p];
@@ -300,11 +300,11 @@ __global__ __launch_bounds__(512) void k_batch_forward_reg(C2<R> *__restrict__ a
 
 // Adjoint sweep on registers: phases and operators last first; a rotation's
 // partial Im <lambda|P|phi> comes from the register pairs it couples, before
-// U^dagger is applied to both states.  Each wavefront leaves its partial in
-// the rotation's LDS slot; after the barrier that opens the next exchange
-// one thread per rotation adds the wavefronts' partials (fixed order), and
-// those reads complete before the exchange's second barrier, after which
-// the next phase writes the slots again.
+// U^dagger is applied to both states.  Each row of 16 lanes leaves its
+// partial in the rotation's LDS slots; after the barrier that opens the next
+// exchange one thread per rotation adds the rows' partials (fixed order),
+// and those reads complete before the exchange's second barrier, after
+// which the next phase writes the slots again.
 template <typename R>
 __global__ __launch_bounds__(512) void k_batch_backward_reg(C2<R> *__restrict__ amps, uint64_t lambda_base,
                                                              const DStep *__restrict__ steps,
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(512) void k_batch_backward_reg(C2<R> *__restrict__ 
                                                              double *__restrict__ gpart)
 {
     extern __shared__ unsigned char lds_raw[];
-    __shared__ double red[kPhaseRotMax][8];
+    __shared__ double red[kPhaseRotMax][kRedRows];
     const uint2 w = work[blockIdx.x];
     const DStep &st = steps[w.x];
     const uint64_t base = insert_zeros(w.y, st.plan);
@@ -374,11 +374,12 @@ struct BlockMap {
 };
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_batch_init(C2<R> *__restrict__ amps, BlockMap bm,
+__global__ __launch_bounds__(256) void k_batch_init(C2<R> *__restrict__ amps, BlockMap bm, const int *__restrict__ blocks,
                                                      const uint64_t *__restrict__ offs, const int *__restrict__ nq)
 {
-    const int c = bm.circ[blockIdx.x];
-    const uint64_t i = bm.start[blockIdx.x] + threadIdx.x;
+    const int blk = blocks[blockIdx.x];
+    const int c = bm.circ[blk];
+    const uint64_t i = bm.start[blk] + threadIdx.x;
     if (i < (1ULL << nq[c])) amps[offs[c] + i] = mk<R>(i == 0 ? R(1) : R(0), R(0));
 }
 
@@ -397,13 +398,25 @@ __global__ __launch_bounds__(256) void k_batch_hamiltonian(C2<R> *__restrict__ a
     if (i < (1ULL << nq[c])) {
         const C2<R> *phi = amps + offs[c];
         double lr = 0.0, li = 0.0;
-        for (int t = term_off[c]; t < term_off[c + 1]; t++) {
-            const DTerm tm = terms[t];
-            const uint64_t j = i ^ tm.x;
-            const double s = (__popcll(j & tm.yz) & 1) ? -1.0 : 1.0;
-            const C2<R> x = phi[j];
-            lr += s * (tm.cre * x.x - tm.cim * x.y);
-            li += s * (tm.cre * x.y + tm.cim * x.x);
+        const int tb = term_off[c], te = term_off[c + 1];
+        // eight terms' gathers in flight before their sums (same order of
+        // additions as one term at a time)
+        constexpr int G = 8;
+        for (int t0 = tb; t0 < te; t0 += G) {
+            C2<R> xs[G];
+#pragma unroll
+            for (int u = 0; u < G; u++)
+                if (t0 + u < te) xs[u] = phi[i ^ terms[t0 + u].x];
+#pragma unroll
+            for (int u = 0; u < G; u++) {
+                if (t0 + u >= te) break;
+                const DTerm tm = terms[t0 + u];
+                const uint64_t j = i ^ tm.x;
+                const double s = (__popcll(j & tm.yz) & 1) ? -1.0 : 1.0;
+                const C2<R> x = xs[u];
+                lr += s * (tm.cre * x.x - tm.cim * x.y);
+                li += s * (tm.cre * x.y + tm.cim * x.x);
+            }
         }
         amps[lambda_base + offs[c] + i] = mk<R>((R)lr, (R)li);
         const C2<R> p = phi[i];
@@ -468,6 +481,8 @@ struct qs_batch {
     int *d_bm_circ = nullptr;
     uint64_t *d_bm_start = nullptr;
     unsigned amp_blocks = 0;
+    int *d_init_blocks = nullptr;   // 256-amplitude blocks of the circuits without steps
+    unsigned init_blocks = 0;
     uint64_t *d_offs = nullptr;
     int *d_nq = nullptr;
     int *d_term_off = nullptr;
@@ -562,13 +577,18 @@ static int launch_phase_kernels(qs_batch *b, bool grads)
                        (const DOp *)b->d_ops, b->num_ops, (const double *)b->d_params, b->d_trig);
     QS_LAUNCH_CHECK();
     // initial states
-    if (b->precision == QS_C64)
-        hipLaunchKernelGGL(k_batch_init<float>, dim3(b->amp_blocks), dim3(256), 0, b->stream, (float2 *)b->amps,
-                           BlockMap{b->d_bm_circ, b->d_bm_start}, (const uint64_t *)b->d_offs, (const int *)b->d_nq);
-    else
-        hipLaunchKernelGGL(k_batch_init<double>, dim3(b->amp_blocks), dim3(256), 0, b->stream, (double2 *)b->amps,
-                           BlockMap{b->d_bm_circ, b->d_bm_start}, (const uint64_t *)b->d_offs, (const int *)b->d_nq);
-    QS_LAUNCH_CHECK();
+    // circuits without operators (a circuit's first step reads |0..0> itself)
+    if (b->init_blocks > 0) {
+        if (b->precision == QS_C64)
+            hipLaunchKernelGGL(k_batch_init<float>, dim3(b->init_blocks), dim3(256), 0, b->stream, (float2 *)b->amps,
+                               BlockMap{b->d_bm_circ, b->d_bm_start}, (const int *)b->d_init_blocks,
+                               (const uint64_t *)b->d_offs, (const int *)b->d_nq);
+        else
+            hipLaunchKernelGGL(k_batch_init<double>, dim3(b->init_blocks), dim3(256), 0, b->stream,
+                               (double2 *)b->amps, BlockMap{b->d_bm_circ, b->d_bm_start}, (const int *)b->d_init_blocks,
+                               (const uint64_t *)b->d_offs, (const int *)b->d_nq);
+        QS_LAUNCH_CHECK();
+    }
     const unsigned rblock = 1u << (b->tile_qubits - 3);   // register path: 8 amplitudes per thread
     for (int p = 0; p < P; p++) {
         if (b->phase_blocks[p] > 0) {
@@ -723,6 +743,9 @@ static void release(qs_batch *b)
     b->d_phases = nullptr;
     f(b->d_bm_circ);
     f(b->d_bm_start);
+    f(b->d_init_blocks);
+    b->d_init_blocks = nullptr;
+    b->init_blocks = 0;
     f(b->d_offs);
     f(b->d_nq);
     f(b->d_term_off);
@@ -841,7 +864,7 @@ static void program_source(std::ostringstream &o, const qs_batch *b, int id, int
         o << "    uint32_t tau = qs::bphase_tau(threadIdx.x, P0);\n    qs::C2<R> x[8];\n";
         o << "    if (active) {\n        const uint64_t xo = base | qs::tile_offset_bits(tau, st);\n"
              "        const qs::RegOffsets ro(P0, st);\n#pragma unroll\n"
-             "        for (int u = 0; u < 8; u++) x[u] = a[xo | ro(u)];\n    }\n";
+             "        for (int u = 0; u < 8; u++) x[u] = qs::load_amp<R>(a, xo | ro(u), st.first);\n    }\n";
         for (int k = 0; k < np; k++) {
             const BPhase &P = b->h_phases[st.ph_begin + k];
             if (k) o << "    tau = qs::bphase_exchange<R>(x, v, tau, P" << k - 1 << ", P" << k << ", active);\n";
@@ -857,7 +880,7 @@ static void program_source(std::ostringstream &o, const qs_batch *b, int id, int
     o << "template <typename R>\n__device__ __forceinline__ void bbwd_" << id
       << "(qs::C2<R> *__restrict__ amps, uint64_t lambda_base, const qs::DStep &st, uint32_t tile, uint64_t base, "
          "const qs::DOp *__restrict__ ops, const double *__restrict__ trig, double *__restrict__ gpart, "
-         "unsigned char *lds, double (*red)[8])\n{\n"
+         "unsigned char *lds, double (*red)[qs::kRedRows])\n{\n"
       << ph.str();
     o << "    qs::C2<R> *vphi = reinterpret_cast<qs::C2<R> *>(lds);\n    qs::C2<R> *vlam = vphi + " << (1u << st.qn)
       << ";\n    qs::C2<R> *a = amps + st.amp_off;\n    qs::C2<R> *l = amps + lambda_base + st.amp_off;\n";
@@ -911,7 +934,7 @@ static std::string launch_source(const qs_batch *b, int s, const std::vector<std
         o << "extern \"C\" __global__ __launch_bounds__(512) void qs_bbwd_" << s << "(" << c2
           << " *__restrict__ amps, unsigned long long lambda_base, const qs::DStep *__restrict__ steps, "
              "const qs::DOp *__restrict__ ops, const uint2 *__restrict__ work, const double *__restrict__ trig, "
-             "double *__restrict__ gpart)\n{\n    __shared__ double red[qs::kPhaseRotMax][8];\n";
+             "double *__restrict__ gpart)\n{\n    __shared__ double red[qs::kPhaseRotMax][qs::kRedRows];\n";
     }
     o << "    using R = " << (f32 ? "float" : "double") << ";\n    extern __shared__ unsigned char lds_raw[];\n";
     o << "    const uint2 w = work[blockIdx.x];\n    const qs::DStep &st = steps[w.x];\n"
@@ -1311,6 +1334,7 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
         for (auto &s : c.steps) {
             DStep d{};
             d.prog = -1;
+            d.first = step_index[ci].empty() ? 1 : 0;
             d.amp_off = c.amp_off;
             std::vector<int> qs_;
             for (int q = 0; q < c.n; q++)
@@ -1491,6 +1515,10 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
     }
     first_block.push_back((int)bm_circ.size());
     b->amp_blocks = (unsigned)bm_circ.size();
+    std::vector<int> init_blocks;
+    for (size_t k = 0; k < bm_circ.size(); k++)
+        if (b->circs[(size_t)bm_circ[k]].steps.empty()) init_blocks.push_back((int)k);
+    b->init_blocks = (unsigned)init_blocks.size();
 
     int rc = QS_OK;
     auto up = [&](auto **dst, const auto &vec) {
@@ -1505,6 +1533,7 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
     up(&b->d_ops, ops);
     up(&b->d_bm_circ, bm_circ);
     up(&b->d_bm_start, bm_start);
+    up(&b->d_init_blocks, init_blocks);
     up(&b->d_offs, offs);
     up(&b->d_nq, nq);
     up(&b->d_term_off, term_off);

@@ -41,7 +41,18 @@ struct DStep {
     int op_begin, op_end;
     int ph_begin, ph_end;   // register phases (steps of >= kRegMinQubits qubits)
     int prog;               // specialised step program of a register-path step (-1: none)
+    int first;              // step 0 of its circuit: reads |0..0> instead of the state
 };
+
+// Amplitude o of a circuit's state at the start of a step: for a circuit's
+// first step the initial state |0..0> (every run starts from it), so that no
+// launch has to write it first.
+template <typename R>
+__device__ __forceinline__ C2<R> load_amp(const C2<R> *__restrict__ a, uint64_t o, bool zero_state)
+{
+    if (zero_state) return mk<R>(o == 0 ? R(1) : R(0), R(0));
+    return a[o];
+}
 
 // Register phases of a step (tiles of at least 2^kRegMinQubits amplitudes):
 // thread t of the block holds the 8 tile coordinates tau(t) | rho(u), where
@@ -100,6 +111,21 @@ __device__ __forceinline__ double bwave_sum(double v)
     __builtin_memcpy(reinterpret_cast<char *>(&r) + 4, &hi, 4);
     return r;
 }
+
+// Sum over each row of 16 lanes (every lane of the row receives it): the
+// first four moves of bwave_sum.
+__device__ __forceinline__ double brow_sum(double v)
+{
+    v += dpp_move<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);       // row_half_mirror
+    v += dpp_move<0x140>(v);       // row_mirror
+    return v;
+}
+
+// Partial sums of a phase's rotations: one per row of 16 lanes (4 per
+// wavefront, 8 wavefronts at most) and gradient slot.
+constexpr int kRedRows = 32;
 
 // 2 x 2 matrix of an operator; dir = -1 gives its adjoint.  A rotation's
 // cos and sin come from the per-operator table trig (filled by k_batch_trig
@@ -394,12 +420,13 @@ __device__ __forceinline__ void fwd_op(C2<R> (&x)[8], const DOp &op, int k, cons
 
 // Operator k of the adjoint sweep (operators last first): a rotation's
 // partial Im <lambda|P|phi> over the thread's register pairs, summed over
-// the wavefront into red[slot][wave], then U^dagger on both tiles.  czm as
+// each row of 16 lanes into red[slot][4 wave + row], then U^dagger on both
+// tiles.  czm as
 // in fwd_op, applied at the run's first CZ (reached last).
 template <typename R>
 __device__ __forceinline__ void bwd_op(C2<R> (&x)[8], C2<R> (&y)[8], const DOp &op, int k,
                                        const double *__restrict__ trig, uint32_t tau, uint64_t base, uint32_t &czm,
-                                       double (*red)[8], int lane, int wave)
+                                       double (*red)[kRedRows], int lane, int wave)
 {
     if (op.kind == BOP_CZ) {
         czm ^= cz_mask(op, tau, base);
@@ -417,8 +444,8 @@ __device__ __forceinline__ void bwd_op(C2<R> (&x)[8], C2<R> (&y)[8], const DOp &
         case 1: reg_grad_pairs<R, 1>(x, y, op.pauli, im); break;
         default: reg_grad_pairs<R, 2>(x, y, op.pauli, im); break;
         }
-        im = bwave_sum(im);
-        if (lane == 0) red[op.slot][wave] = im;
+        im = brow_sum(im);
+        if ((lane & 15) == 15) red[op.slot][4 * wave + (lane >> 4)] = im;
     }
     if (op.kind == BOP_ROT) {
         const R c = (R)trig[2 * k], sn = -(R)trig[2 * k + 1];   // the adjoint
@@ -433,17 +460,17 @@ __device__ __forceinline__ void bwd_op(C2<R> (&x)[8], C2<R> (&y)[8], const DOp &
 }
 
 // Thread 0.. of the block: the rotation partials of the finished phase
-// [op_begin, op_end) summed over the wavefronts (fixed order) into gpart,
-// one thread per operator.
+// [op_begin, op_end) summed over the rows of the wavefronts (fixed order)
+// into gpart, one thread per operator.
 __device__ __forceinline__ void flush_phase(const DOp *__restrict__ ops, int op_begin, int op_end,
-                                            const double (*red)[8], int nwaves, uint32_t tile,
+                                            const double (*red)[kRedRows], int nwaves, uint32_t tile,
                                             double *__restrict__ gpart)
 {
     for (int i = (int)threadIdx.x; i < op_end - op_begin; i += (int)blockDim.x) {
         const DOp &op = ops[op_begin + i];
         if (op.grad < 0) continue;
         double v = 0.0;
-        for (int w = 0; w < nwaves; w++) v += red[op.slot][w];
+        for (int w = 0; w < 4 * nwaves; w++) v += red[op.slot][w];
         gpart[op.gpart + tile] = v;
     }
 }

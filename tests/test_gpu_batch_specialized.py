@@ -124,3 +124,26 @@ def test_specialize_requires_compiled(qs):
         b.specialize()
     with pytest.raises(ValueError):
         qs.native.qs_batch_specialize(b._b)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_batch_circuits_without_operators(qs, prec):
+    """Circuits with no operators keep |0..0> (the only ones the initial-state
+    kernel writes; a circuit's first step reads |0..0> itself), also on a
+    second run after an adjoint sweep and with specialised steps."""
+    rng = np.random.default_rng(83)
+    probs = [hea_problem(rng, n, 1) for n in (4, 10, 11)]
+    for p in probs[:2]:
+        p["ops"], p["angles"] = [], np.zeros(0)
+    b = build(qs, probs, prec)
+    b.specialize()
+    params = np.concatenate([p["angles"] for p in probs])
+    for grads in (True, False):
+        e, _ = b.run(params, grads=grads)
+        for i, p in enumerate(probs):
+            psi = oracle.run_ops(oracle.zero_state(p["n"]), p["ops"])
+            we = oracle.sv_expec_pauli_sum(psi, p["codes"], p["coeffs"]).real
+            assert abs(e[i] - we) < TOL[prec] * max(1.0, np.abs(p["coeffs"]).sum()), (p["n"], grads)
+    for i, p in enumerate(probs):
+        psi = oracle.run_ops(oracle.zero_state(p["n"]), p["ops"])
+        assert amp_err(b.state(i), psi) < TOL[prec], p["n"]
