@@ -112,14 +112,30 @@ __device__ __forceinline__ double bwave_sum(double v)
     return r;
 }
 
-// Sum over each row of 16 lanes (every lane of the row receives it): the
-// first four moves of bwave_sum.
+// v moved within rows of 16 lanes by a DPP control whose every lane has a
+// source lane in its row (quad permutes, mirrors): no old value is kept.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row_move(double v)
+{
+    int lo, hi;
+    __builtin_memcpy(&lo, &v, 4);
+    __builtin_memcpy(&hi, reinterpret_cast<const char *>(&v) + 4, 4);
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, true);
+    double r;
+    __builtin_memcpy(&r, &lo, 4);
+    __builtin_memcpy(reinterpret_cast<char *>(&r) + 4, &hi, 4);
+    return r;
+}
+
+// Sum over each row of 16 lanes (every lane of the row receives it), all
+// lanes active: quad permutes and mirrors as in bwave_sum.
 __device__ __forceinline__ double brow_sum(double v)
 {
-    v += dpp_move<0xB1>(v);        // quad_perm [1, 0, 3, 2]
-    v += dpp_move<0x4E>(v);        // quad_perm [2, 3, 0, 1]
-    v += dpp_move<0x141>(v);       // row_half_mirror
-    v += dpp_move<0x140>(v);       // row_mirror
+    v += dpp_row_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_row_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_row_move<0x141>(v);   // row_half_mirror
+    v += dpp_row_move<0x140>(v);   // row_mirror
     return v;
 }
 
@@ -198,9 +214,10 @@ __device__ __forceinline__ void reg_pairs(C2<R> (&x)[8], C2<R> m0, C2<R> m1, C2<
 // Partial of Im <lambda|P|phi> over the register pairs (u0, u0 | 1 << J) of a
 // rotation exp(i theta P) on register bit J.
 template <typename R, int J>
-__device__ __forceinline__ void reg_grad_pairs(const C2<R> (&x)[8], const C2<R> (&y)[8], int pauli, double &im)
+__device__ __forceinline__ double reg_grad_pairs(const C2<R> (&x)[8], const C2<R> (&y)[8], int pauli)
 {
 #pragma clang fp contract(off)
+    double im = 0.0;
 #pragma unroll
     for (int u0 = 0; u0 < 8; u0++) {
         if ((u0 >> J) & 1) continue;
@@ -224,11 +241,13 @@ __device__ __forceinline__ void reg_grad_pairs(const C2<R> (&x)[8], const C2<R> 
         v = fma(l1.x, p1.y, v);
         v = fma(-l0.y, p0.x, v);
         v = fma(l0.x, p0.y, v);
-        im += (double)v;
+        if (u0 == 0) im = (double)v;   // the first pair (u0 = 0 never has bit J)
+        else im += (double)v;
     }
     if constexpr (J == 0) asm volatile("; grad pairs 0");
     else if constexpr (J == 1) asm volatile("; grad pairs 1");
     else asm volatile("; grad pairs 2");
+    return im;
 }
 
 // Rotation c 1 + i s P (P = X, Y, Z by PA = 1, 2, 3) on the register pairs
@@ -438,11 +457,11 @@ __device__ __forceinline__ void bwd_op(C2<R> (&x)[8], C2<R> (&y)[8], const DOp &
         return;
     }
     if (op.grad >= 0) {
-        double im = 0.0;
+        double im;
         switch (op.rbit) {
-        case 0: reg_grad_pairs<R, 0>(x, y, op.pauli, im); break;
-        case 1: reg_grad_pairs<R, 1>(x, y, op.pauli, im); break;
-        default: reg_grad_pairs<R, 2>(x, y, op.pauli, im); break;
+        case 0: im = reg_grad_pairs<R, 0>(x, y, op.pauli); break;
+        case 1: im = reg_grad_pairs<R, 1>(x, y, op.pauli); break;
+        default: im = reg_grad_pairs<R, 2>(x, y, op.pauli); break;
         }
         im = brow_sum(im);
         if ((lane & 15) == 15) red[op.slot][4 * wave + (lane >> 4)] = im;
