@@ -383,6 +383,8 @@ __global__ __launch_bounds__(256) void k_batch_init(C2<R> *__restrict__ amps, Bl
     if (i < (1ULL << nq[c])) amps[offs[c] + i] = mk<R>(i == 0 ? R(1) : R(0), R(0));
 }
 
+constexpr int kTermGroup = 4;   // Hamiltonian terms gathered together
+
 // lambda = H phi with (P phi)_i = beta_{i^x} phi_{i^x}, beta_y = i^{#Y} (-1)^{popc(y & yz)};
 // energy partial sum_i conj(phi_i) lambda_i per block.
 template <typename R>
@@ -399,20 +401,21 @@ __global__ __launch_bounds__(256) void k_batch_hamiltonian(C2<R> *__restrict__ a
         const C2<R> *phi = amps + offs[c];
         double lr = 0.0, li = 0.0;
         const int tb = term_off[c], te = term_off[c + 1];
-        // eight terms' gathers in flight before their sums (same order of
-        // additions as one term at a time)
-        constexpr int G = 8;
+        // indices within a circuit of at most 30 qubits: 32-bit
+        const uint32_t i32 = (uint32_t)i;
+        // a group's gathers in flight before their sums (same order of
+        // additions as one term at a time; the host pads every circuit's
+        // terms to whole groups with zero terms)
+        constexpr int G = kTermGroup;
         for (int t0 = tb; t0 < te; t0 += G) {
             C2<R> xs[G];
 #pragma unroll
-            for (int u = 0; u < G; u++)
-                if (t0 + u < te) xs[u] = phi[i ^ terms[t0 + u].x];
+            for (int u = 0; u < G; u++) xs[u] = phi[i32 ^ (uint32_t)terms[t0 + u].x];
 #pragma unroll
             for (int u = 0; u < G; u++) {
-                if (t0 + u >= te) break;
                 const DTerm tm = terms[t0 + u];
-                const uint64_t j = i ^ tm.x;
-                const double s = (__popcll(j & tm.yz) & 1) ? -1.0 : 1.0;
+                const uint32_t j = i32 ^ (uint32_t)tm.x;
+                const double s = (__popc(j & (uint32_t)tm.yz) & 1) ? -1.0 : 1.0;
                 const C2<R> x = xs[u];
                 lr += s * (tm.cre * x.x - tm.cim * x.y);
                 li += s * (tm.cre * x.y + tm.cim * x.x);
@@ -1511,6 +1514,8 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
             d.cim = cf.imag();
             terms.push_back(d);
         }
+        // padded with zero terms to whole groups of the gather kernel
+        while ((terms.size() - (size_t)term_off.back()) % kTermGroup) terms.push_back(DTerm{});
         term_off.push_back((int)terms.size());
     }
     first_block.push_back((int)bm_circ.size());
