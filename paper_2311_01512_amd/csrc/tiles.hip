@@ -22,7 +22,10 @@
 #include "tile_dev.hpp"
 
 #include <algorithm>
+#include <cstdlib>
+#include <deque>
 #include <map>
+#include <string>
 #include <mutex>
 #include <tuple>
 #include <type_traits>
@@ -192,8 +195,111 @@ static void mfma_coeffs(const std::vector<cd> &G, int k, std::vector<cd> &out)
 }
 
 // Operators of a finished step in the step's coordinates, grouped in phases.
-static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircOp *> &members, bool mfma)
+// Member fusion: an uncontrolled dense gate whose targets lie inside those
+// of another uncontrolled dense gate of the step joins it as one operator,
+// the FP64 product of the two, when every member between them commutes with
+// the one that moves (so the product applies at the other's place).  Fewer
+// operators, the same map: a one-qubit gate next to a two-qubit gate on that
+// qubit, or a density matrix's U and conj(U) next to a channel on (t, t + N),
+// cost one matrix instead of two or three.  QS_TILE_FUSE=0 turns it off.
+static bool tile_fuse_enabled()
 {
+    static const bool on = [] {
+        const char *e = std::getenv("QS_TILE_FUSE");
+        return !(e && std::string(e) == "0");
+    }();
+    return on;
+}
+
+// A's matrix on the target list `tt` (a superset of A's targets): identity
+// on the others.  Matrices are row-major, bit q of an index <-> target q.
+static std::vector<cd> embed_matrix(const CircOp &a, const std::vector<int> &tt)
+{
+    const size_t D = (size_t)1 << tt.size(), Da = (size_t)1 << a.targs.size();
+    std::vector<int> pos(a.targs.size());
+    uint32_t amask = 0;
+    for (size_t q = 0; q < a.targs.size(); q++) {
+        pos[q] = (int)(std::find(tt.begin(), tt.end(), a.targs[q]) - tt.begin());
+        amask |= 1u << pos[q];
+    }
+    auto sub = [&](size_t r) {
+        size_t v = 0;
+        for (size_t q = 0; q < pos.size(); q++) v |= ((r >> pos[q]) & 1u) << q;
+        return v;
+    };
+    std::vector<cd> m(D * D, cd(0, 0));
+    for (size_t r = 0; r < D; r++)
+        for (size_t c = 0; c < D; c++)
+            if ((r & ~(size_t)amask) == (c & ~(size_t)amask)) m[r * D + c] = a.M[sub(r) * Da + sub(c)];
+    return m;
+}
+
+static std::vector<const CircOp *> fuse_members(const std::vector<const CircOp *> &in, std::deque<CircOp> &store)
+{
+    std::vector<const CircOp *> L = in;
+    if (!tile_fuse_enabled()) return L;
+    auto dense = [](const CircOp *o) { return !o->gadget && o->ctrls.empty(); };
+    auto inside = [](const CircOp *a, const CircOp *b) {   // targets of a within those of b
+        for (int t : a->targs)
+            if (std::find(b->targs.begin(), b->targs.end(), t) == b->targs.end()) return false;
+        return true;
+    };
+    std::vector<char> alive(L.size(), 1);
+    for (bool changed = true; changed;) {
+        changed = false;
+        for (size_t j = 0; j < L.size(); j++) {
+            if (!alive[j] || !dense(L[j])) continue;
+            const CircOp *X = L[j];
+            const OpMasks mx = op_masks(*X);
+            for (size_t i = j; i-- > 0;) {
+                if (!alive[i]) continue;
+                const CircOp *Y = L[i];
+                if (dense(Y) && (inside(Y, X) || inside(X, Y))) {
+                    const bool fwd = inside(Y, X);   // Y moves forward to X, else X back to Y
+                    const OpMasks mm = op_masks(fwd ? *Y : *X);
+                    bool ok = true;
+                    for (size_t k = i + 1; k < j && ok; k++)
+                        if (alive[k] && !ops_commute(mm, op_masks(*L[k]))) ok = false;
+                    if (ok) {
+                        CircOp f;
+                        f.gadget = false;
+                        f.theta = 0.0;
+                        f.targs = fwd ? X->targs : Y->targs;
+                        const size_t D = (size_t)1 << f.targs.size();
+                        const std::vector<cd> a = embed_matrix(*Y, f.targs), b = embed_matrix(*X, f.targs);
+                        f.M.assign(D * D, cd(0, 0));
+                        for (size_t r = 0; r < D; r++)   // X after Y: b a
+                            for (size_t k = 0; k < D; k++) {
+                                const cd brk = b[r * D + k];
+                                if (brk == cd(0, 0)) continue;
+                                for (size_t c = 0; c < D; c++) f.M[r * D + c] += brk * a[k * D + c];
+                            }
+                        store.push_back(std::move(f));
+                        if (fwd) {
+                            L[j] = &store.back();
+                            alive[i] = 0;
+                        } else {
+                            L[i] = &store.back();
+                            alive[j] = 0;
+                        }
+                        changed = true;
+                    }
+                    break;
+                }
+                if (!ops_commute(op_masks(*Y), mx)) break;
+            }
+        }
+    }
+    std::vector<const CircOp *> out;
+    for (size_t k = 0; k < L.size(); k++)
+        if (alive[k]) out.push_back(L[k]);
+    return out;
+}
+
+static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircOp *> &recorded, bool mfma)
+{
+    std::deque<CircOp> fused;
+    const std::vector<const CircOp *> members = fuse_members(recorded, fused);
     p.tile = true;
     p.gadget = false;
     p.basis.clear();
@@ -517,7 +623,7 @@ static void encode_step(Pass &p, const Echelon &E, const std::vector<const CircO
             p.phases.back().num_ops++;
         }
     }
-    p.members = (int)members.size();
+    p.members = (int)recorded.size();
 }
 
 void plan_tiles(qs_circuit *c, int T, int precision)

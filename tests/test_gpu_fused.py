@@ -317,3 +317,44 @@ def test_tiles_move_commuting_operators(qs, k, prec):
         q.set_amps(psi)
         circ.apply(q)
         assert amp_err(q.get_amps(), want) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("k", [8, 10])
+def test_tile_member_fusion(qs, prec, k):
+    """Operators that tile steps fuse into one matrix (uncontrolled gates whose
+    targets nest inside another's, with commuting operators between them)
+    next to ones they must not fuse with (a controlled gate or a gadget on
+    the same qubit in between), against the oracle, generic and specialised."""
+    banner(f"tile member fusion {prec} k={k}")
+    N = 11
+    rng = np.random.default_rng(910 + k)
+
+    def u(targs, ctrls=()):
+        return {"op": "unitary", "ctrls": tuple(ctrls), "targs": tuple(targs),
+                "matrix": synth.haar_unitary(rng, 1 << len(targs))}
+
+    ops = []
+    for rep in range(12):
+        a, b, c, d, e = (int(x) for x in rng.permutation(N)[:5])
+        # u(a) joins u(a, b) across the commuting u(d); u(b) joins it too
+        ops += [u([a]), u([d]), u([a, b]), u([b]), u([e, d])]
+        # the controlled gate on a is not fused, and nothing on a fuses across it
+        ops += [u([b, a]), u([a], [c]), u([a])]
+        # nor across the gadget on c and e
+        ops += [u([c]), {"op": "gadget", "targs": (c, e), "paulis": (1, 3), "theta": 0.3 + rep}, u([c, e])]
+        # nested target sets of 1 to 4 qubits (4: the matrix cores in complex64)
+        ops += [u([a, b, c]), u([c]), u([b, a]), u([a, b, c, d]), u([d]), u([b, d])]
+    psi = synth.random_state(rng, 1 << N)
+    want = oracle.run_ops(psi.copy(), ops)
+    circ = qs.Circuit(N, ops).compile(k, prec)
+    kinds = [circ.pass_info(i)["kernel"] for i in range(circ.stats()["num_passes"])]
+    assert kinds.count("tile") >= 1
+    q = qs.Qureg(N, precision=prec).set_amps(psi)
+    circ.apply(q)
+    generic = q.get_amps()
+    assert amp_err(generic, want) < TOL[prec]
+    circ.specialize()
+    q.set_amps(psi)
+    circ.apply(q)
+    assert np.array_equal(q.get_amps(), generic)
