@@ -258,6 +258,36 @@ def cpu_baseline(ops, n, seed, runs):
     return rec, psi
 
 
+def batch_vs_oracle(keep):
+    """The batch's energies of a sample of circuits (the smallest, the
+    largest and two between) against the oracle's, and the gradient of the
+    smallest against the oracle's exact parameter-shift rule, on the host."""
+    import numpy as np
+    import oracle
+    probs, e, g = keep["probs"], keep["energies"], keep["grads"]
+    ns = [p["num_qubits"] for p in probs]
+    order = sorted(range(len(probs)), key=lambda i: (ns[i], i))
+    sample = sorted({order[0], order[len(order) // 3], order[2 * len(order) // 3], order[-1]})
+    offs = np.concatenate([[0], np.cumsum([len(p["angles"]) for p in probs])])
+    t0 = time.perf_counter()
+    e_err = 0.0
+    for i in sample:
+        p = probs[i]
+        psi = oracle.run_ops(oracle.zero_state(p["num_qubits"]), p["ops"])
+        want = oracle.sv_expec_pauli_sum(psi, p["codes"], p["coeffs"]).real
+        e_err = max(e_err, abs(e[i] - want) / max(1.0, float(np.abs(p["coeffs"]).sum())))
+    i0 = order[0]
+    p = probs[i0]
+    m = len(p["angles"])
+    gw = oracle.param_shift_gradient(p["num_qubits"], p["ops"], p["codes"], p["coeffs"], m)
+    g_err = float(np.abs(g[offs[i0]:offs[i0] + m] - gw).max() / max(1.0, float(np.abs(gw).max())))
+    return {"max_energy_err": float(e_err), "max_grad_err": g_err,
+            "sample": f"energies of circuits {sample} (N = {[ns[i] for i in sample]}), scaled by the sum of "
+                      f"|coefficients|; the {m} gradients of circuit {i0} (N = {ns[i0]}) against the exact "
+                      f"parameter-shift rule, scaled by their largest magnitude",
+            "seconds": time.perf_counter() - t0}
+
+
 def streaming_ceiling(qs, q, torch, reps=5):
     """The fastest in-house streaming kernel on this state: a Pauli-X gadget
     on the highest qubit (k_gadget_pairs: each thread reads and writes a
@@ -539,7 +569,7 @@ def bench_density(args, torch, qs, synth):
     return line
 
 
-def bench_batch(args, torch, qs, synth):
+def bench_batch(args, torch, qs, synth, keep=None):
     """512 hardware-efficient-ansatz circuits, N ~ U{10..22}, 6 layers, 20-term
     Pauli-sum energies and adjoint gradients over all angles, one graph replay."""
     import numpy as np
@@ -577,6 +607,8 @@ def bench_batch(args, torch, qs, synth):
         spec["used"] = "generic"
     full, (e, g) = timed(True)
     fwd, _ = timed(False)
+    if keep is not None:   # for the check against the oracle on the host
+        keep.update({"probs": probs, "energies": np.array(e), "grads": np.array(g)})
     fwd_upd = st["logical_updates"]
     total = 3 * fwd_upd      # forward, then U^dagger on phi and on lambda
     # algorithmic FP32 flops of one run, each operator at the fewest flops
@@ -787,7 +819,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_workloads:
         result["density14"] = bench_density(args, torch, qs, synth)
-        result["batch512"] = bench_batch(args, torch, qs, synth)
+        batch_keep = {}
+        result["batch512"] = bench_batch(args, torch, qs, synth, batch_keep)
     if not args.no_cpu_baseline:
         base, psi = cpu_baseline(ops, n, seed, args.cpu_runs)
         result["cpu_baseline"] = base
@@ -801,6 +834,8 @@ def main():
         result["plain_c128"]["max_amp_err_vs_oracle"] = errs["plain_c128"]
         result["fused_c128"]["max_amp_err_vs_oracle"] = errs["fused_c128"]
         del want
+        if not args.no_workloads:
+            result["batch512"]["vs_oracle"] = batch_vs_oracle(batch_keep)
     print(json.dumps(result), flush=True)
 
 
