@@ -1300,7 +1300,9 @@ int qs_batch_compile(qs_batch *b, void *hip_stream, int use_graph)
         QS_HIP(hipGetDevice(&dev));
         QS_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         b->tile_qubits = b->precision == QS_C64 ? 12 : 11;
-        while (b->tile_qubits > b->low_qubits + 1 && (2 * ((size_t)1 << b->tile_qubits) * ab + 512) > (size_t)max_lds)
+        // the adjoint sweep's two tiles and its partial sums
+        const size_t red = sizeof(double) * kPhaseRotMax * kRedRows;
+        while (b->tile_qubits > b->low_qubits + 1 && (2 * ((size_t)1 << b->tile_qubits) * ab + red) > (size_t)max_lds)
             b->tile_qubits--;
     }
     const int TQ = b->tile_qubits, C = b->low_qubits;
