@@ -373,6 +373,7 @@ struct BlockMap {
     const uint64_t *start;   // first local index of each block
 };
 
+// |0..0> in the listed 256-amplitude blocks.
 template <typename R>
 __global__ __launch_bounds__(256) void k_batch_init(C2<R> *__restrict__ amps, BlockMap bm, const int *__restrict__ blocks,
                                                      const uint64_t *__restrict__ offs, const int *__restrict__ nq)
@@ -579,8 +580,8 @@ static int launch_phase_kernels(qs_batch *b, bool grads)
     hipLaunchKernelGGL(k_batch_trig, dim3((unsigned)((b->num_ops + 255) / 256)), dim3(256), 0, b->stream,
                        (const DOp *)b->d_ops, b->num_ops, (const double *)b->d_params, b->d_trig);
     QS_LAUNCH_CHECK();
-    // initial states
-    // circuits without operators (a circuit's first step reads |0..0> itself)
+    // |0..0> for circuits without operators (a circuit's first step reads
+    // |0..0> itself)
     if (b->init_blocks > 0) {
         if (b->precision == QS_C64)
             hipLaunchKernelGGL(k_batch_init<float>, dim3(b->init_blocks), dim3(256), 0, b->stream, (float2 *)b->amps,
