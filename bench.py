@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+FP64_VECTOR_PEAK_TFLOPS = 78.6    # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 
 
 def parse():
@@ -63,6 +64,8 @@ def parse():
                     help="compile the probe circuit's tile steps into a kernel each first")
     ap.add_argument("--no-specialize", action="store_true",
                     help="keep the generic tile-step kernel (no run-time compilation)")
+    ap.add_argument("--batch-precision", default="c64", choices=["c64", "c128"],
+                    help="state precision of the batch512 workload")
     ap.add_argument("--workload", default="circuit28", choices=["circuit28", "density14", "batch512", "sv34"],
                     help="circuit28 (default, the headline): 28-qubit 500-gate circuit; density14: 14-qubit "
                          "density matrix; batch512: 512 circuits with energies and gradients; sv34: 34 qubits")
@@ -574,7 +577,7 @@ def bench_batch(args, torch, qs, synth, keep=None):
     Pauli-sum energies and adjoint gradients over all angles, one graph replay."""
     import numpy as np
     probs = synth.config4_batch()
-    b = qs.Batch("c64")
+    b = qs.Batch(args.batch_precision)
     for p in probs:
         b.add_circuit(p["num_qubits"], p["ops"], len(p["angles"]), p["codes"], p["coeffs"])
     b.compile()
@@ -611,7 +614,7 @@ def bench_batch(args, torch, qs, synth, keep=None):
         keep.update({"probs": probs, "energies": np.array(e), "grads": np.array(g)})
     fwd_upd = st["logical_updates"]
     total = 3 * fwd_upd      # forward, then U^dagger on phi and on lambda
-    # algorithmic FP32 flops of one run, each operator at the fewest flops
+    # algorithmic flops of one run (FP32 or FP64), each operator at the fewest flops
     # its form needs per amplitude: a rotation c 1 + i s P (P = X, Y, Z) 6
     # (one product and one fused multiply-add per real component), a fixed
     # 2 x 2 gate 14 (two complex products and a sum), CZ none; the adjoint
@@ -626,11 +629,13 @@ def bench_batch(args, torch, qs, synth, keep=None):
         fixed += sum(1 for op in p["ops"] if op["op"] == "gadget" and "param" not in op)
         flops += a * (3 * (6 * rot + 14 * fixed) + 4 * rot + 8 * len(p["coeffs"]))
     achieved = flops / full / 1e12
-    roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+    peak = FP32_VECTOR_PEAK_TFLOPS if args.batch_precision == "c64" else FP64_VECTOR_PEAK_TFLOPS
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None,
             "kernel": "batch replay (forward, energies, adjoint sweep; states stay in LDS / L2)",
             "flops_per_run": flops}
-    return base_line(total / full, "amplitude-updates/s", args.steps, args.warmup, full * 1e3, "c64 (f32)",
+    return base_line(total / full, "amplitude-updates/s", args.steps, args.warmup, full * 1e3,
+                     "c64 (f32)" if args.batch_precision == "c64" else "c128 (f64)",
                      "512 statevectors, N ~ U{10..22}, 6-layer hardware-efficient ansatz, 20-term Pauli-sum "
                      "energy and adjoint gradient over all angles, one HIP-graph replay",
                      {"roofline": roof, "circuits": st["num_circuits"], "total_amplitudes": st["total_amps"],
